@@ -1,0 +1,205 @@
+/* libaps -- sub-1-spp adaptive sampling and gathering-pyramid reconstruction on MI355X.
+ *
+ * C ABI of the per-frame hot path of "Forget Superresolution, Sample Adaptively (when
+ * Path Tracing)" (arXiv 2602.08642).  Every entry point:
+ *   - takes DEVICE pointers owned by the caller (no pointer is retained after return),
+ *     NHWC contiguous, batch-major, 16-byte aligned;
+ *   - enqueues its kernels on `stream` (a hipStream_t; NULL = the null stream) and never
+ *     synchronises;
+ *   - validates its arguments on the host first and returns an aps_status code; nothing
+ *     is launched when the code is not APS_OK.  Conditions only the device can see set
+ *     bits in the optional caller-provided `dev_status` word (APS_STATUS_*), via atomic OR;
+ *   - allocates nothing: scratch comes from the caller's workspace `ws` of `ws_bytes`
+ *     (query with the matching *_workspace_size function).
+ * An empty problem (N, H or W == 0) returns APS_OK after the size checks, before any pointer
+ * check, and launches nothing (aps_sample_mask only sets *total = 0).
+ * Radiance buffers are RGBA float32 (16-byte pixels, A unused and written as 0).
+ * Densities, counts and offsets are indexed by the global pixel id n*H*W + y*W + x.
+ */
+#ifndef APS_H
+#define APS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum aps_status {
+  APS_OK = 0,
+  APS_ERR_NULL = 1,        /* a required pointer is NULL */
+  APS_ERR_SHAPE = 2,       /* sizes inconsistent or outside the documented limits */
+  APS_ERR_UNSUPPORTED = 3, /* a kernel size / dtype / level count with no compiled kernel */
+  APS_ERR_WORKSPACE = 4,   /* ws missing or smaller than the query returns */
+  APS_ERR_HIP = 5,         /* a HIP launch or runtime call failed */
+  APS_ERR_ARG = 6          /* a scalar argument is out of range */
+};
+
+enum aps_dtype { APS_F32 = 0, APS_BF16 = 1 };
+enum aps_mode { APS_HARD = 0, APS_RELAXED = 1 };
+enum aps_feature_kind { APS_FEAT_SAMPLER = 0, APS_FEAT_KERNEL = 1 };
+enum aps_conv_mode { APS_CONV_DIRECT = 0, APS_CONV_POOL2 = 1, APS_CONV_UP2_CAT = 2 };
+
+#define APS_MAX_LEVELS 5
+#define APS_MAX_NET_LAYERS 20
+
+/* device status bits */
+#define APS_STATUS_COUNT_OVERFLOW 1u /* floor(s) > 254: count clamped to 255 */
+#define APS_STATUS_NONFINITE 2u      /* a density was NaN, infinite or negative */
+#define APS_STATUS_CAPACITY 4u       /* the sample list capacity was too small */
+
+const char* aps_status_string(int status);
+int aps_version(void); /* major*10000 + minor*100 + patch */
+
+/* ---------------------------------------------------------------- networks
+ * One conv layer: packed weights (aps_conv_pack_weights), bias [cout] float32.
+ * A network is an ordered list of layers sharing one compute dtype.
+ *   sampler CNN (3 layers):  d0 (C->16, ReLU), d1 (16->16, ReLU), d2 (16->1)
+ *   U-Net (14 + n_heads):    enc0a enc0b enc1a enc1b enc2a enc2b bota botb
+ *                            dec2a dec2b dec1a dec1b dec0a dec0b head0 .. head{n-1}
+ */
+typedef struct {
+  const void* w;
+  const float* b;
+  int cin, cout, ksize, relu;
+} aps_conv_layer;
+
+typedef struct {
+  int n_layers;
+  int dtype; /* APS_F32 or APS_BF16: weights and activations; accumulation is fp32 */
+  aps_conv_layer layer[APS_MAX_NET_LAYERS];
+} aps_net;
+
+/* Elements of the packed weight buffer of one layer (0 for unsupported sizes). */
+size_t aps_conv_packed_elems(int Cout, int ksize, int Cin);
+
+/* Pack OHWI float32 weights w[Cout][k][k][Cin] (device) into MFMA fragment order, in
+ * dtype (bf16: round to nearest even).  packed holds aps_conv_packed_elems elements. */
+int aps_conv_pack_weights(const float* w, int Cout, int ksize, int Cin, int dtype, void* packed,
+                          void* stream);
+
+/* 'Same' convolution (ksize 1 or 3, zero padding) + bias (+ ReLU), NHWC, output [N,H,W]
+ * with row stride ldy >= Cout channels (channels [Cout, round_up(Cout,4)) are written 0 when
+ * ldy allows).  Input transform `mode`:
+ *   APS_CONV_DIRECT : x [N,H,W,Cx]
+ *   APS_CONV_POOL2  : x [N,2H,2W,Cx], 2x2 average-pooled on the fly
+ *   APS_CONV_UP2_CAT: x [N,H/2,W/2,Cx] nearest-2x upsampled, concatenated with x2 [N,H,W,C2]
+ *                     (channels [0,Cx) from x, [Cx,Cx+C2) from x2)
+ * Cx and C2 must be multiples of 8.  dtype/y_dtype: (F32,F32), (BF16,BF16) or (BF16,F32). */
+int aps_conv2d_fwd(const void* x, const void* x2, int N, int H, int W, int Cx, int C2, int mode,
+                   const void* packed_w, const float* bias, int Cout, int ksize, int relu,
+                   int dtype, void* y, int ldy, int y_dtype, void* stream);
+
+/* ---------------------------------------------------------------- a1 + a2: density
+ * Sec. 3 (Overview): the sampler predicts one channel z; s = f*B + (1-f)*B*Npx*softmax(z)
+ * with the softmax over the H*W pixels of each frame, so sum(s) = Npx*B and s >= f*B
+ * (f = 1/8 in the paper).  The reduction is a fixed tree: results are deterministic. */
+size_t aps_normalize_workspace_size(int N, int H, int W);
+int aps_normalize_density(const float* z, int N, int H, int W, float budget_spp,
+                          float uniform_frac, float* s_out, void* ws, size_t ws_bytes,
+                          uint32_t* dev_status, void* stream);
+
+/* Sampler CNN on features feat [N,H,W,C] (dtype of the net) -> z (optional, float32 [N,H,W])
+ * -> s float32 [N,H,W]. */
+size_t aps_density_predict_workspace_size(int N, int H, int W, int width, int dtype);
+int aps_density_predict(const aps_net* net, const void* feat, int N, int H, int W, int C,
+                        float budget_spp, float uniform_frac, float* z_out, float* s_out,
+                        void* ws, size_t ws_bytes, uint32_t* dev_status, void* stream);
+
+/* ---------------------------------------------------------------- a3: sample mask
+ * Sec. 4.2, eq. holdout: count = floor(s) + [u < p], p = s - floor(s) (exact in binary32),
+ * u = (Philox4x32-10(key = seed, counter = (pixel, frame, 0, 0)).x >> 8) * 2^-24.
+ * Outputs: count uint8 [N,H,W]; pixel_offset int32 [N,H,W] = exclusive prefix sum of count
+ * in pixel order; sample_pixel int32 [capacity] = the pixel id of every requested sample,
+ * ascending (the renderer's request list); total int32 (device) = sum of counts; p_out
+ * (optional) float32 [N,H,W].  Bit-exact and deterministic.  N*H*W < 2^31.
+ * Capacity N*H*W*(B + 1) always suffices for budget-normalised s; entries past capacity are
+ * dropped and flagged APS_STATUS_CAPACITY. */
+size_t aps_sample_mask_workspace_size(int N, int H, int W);
+int aps_sample_mask(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                    uint8_t* count, int32_t* pixel_offset, int32_t* sample_pixel,
+                    int64_t capacity, int32_t* total, float* p_out, void* ws, size_t ws_bytes,
+                    uint32_t* dev_status, void* stream);
+
+/* Renderer stand-in (not part of the method): writes sample j of pixel i as
+ * pool[i][j mod J] (pool float32 [N*H*W][J][4]) at samples[pixel_offset[i] + j]. */
+int aps_fixture_render(const float* pool, int J, const uint8_t* count,
+                       const int32_t* pixel_offset, int N, int H, int W, int64_t capacity,
+                       float* samples, void* stream);
+
+/* ---------------------------------------------------------------- a4: scatter + pyramid
+ * Sec. 4.2 eq. stoch_rnoisy: L0 = (sum_{j<floor(s)} S_j + H) / s (0 where s == 0), with
+ * the holdout S_floor(s) taken iff count > floor(s):
+ *   APS_HARD:    H = S_floor(s)
+ *   APS_RELAXED: H = S_floor(s) * h * clamp(lambda * (p - u) / p, 0, 1), h = 2 lambda/(2 lambda - 1)
+ *   (Sec. 4.3 eqs. relaxed_holdout, h_factor, with the variate mirrored u -> 1 - u so the
+ *    ramp is non-zero exactly when u < p; u is regenerated from (seed, frame)).
+ * App. A eq. app-pyramid: L[l] = 2^l x 2^l block means of L0, l < levels.
+ * samples float32 [n_samples][4] in request order (entries at or past n_samples, which
+ * only a mask that overflowed its capacity requests, contribute 0); L[l] float32 RGBA
+ * [N, H>>l, W>>l].  H and W must be divisible by 2^(levels-1). */
+int aps_scatter_samples(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                        const float* samples, int64_t n_samples, int N, int H, int W, int levels,
+                        int mode,
+                        float lambda, uint64_t seed, uint32_t frame, float* const* L,
+                        void* stream);
+
+/* Network inputs (C <= 16 channels, zero padded), out [N,H,W,C] in out_dtype.
+ *   APS_FEAT_SAMPLER: aux[0..6], then with prev: tonemap(W prev) RGB, valid
+ *   APS_FEAT_KERNEL : aux[0..6], slog1p(L0) RGB, s, then with prev: slog1p(W prev) RGB, valid
+ * aux float32 [N,H,W,8] (albedo 3, normal 3, log-depth 1, pad); W prev = bilinear warp of the
+ * previous output along mv (see aps_reproject); valid = the back-projected position lies in
+ * the frame; slog1p(v) = sign(v) log(1+|v|); tonemap = the evaluation filmic curve of Sec. 5
+ * (s = h = 0.5, contrast 0.4, exposure 0, saturation 1) followed by the sRGB transfer. */
+int aps_assemble_features(int kind, const float* aux, const float* L0, const float* s,
+                          const float* prev, const float* mv, int N, int H, int W, int C,
+                          int out_dtype, void* out, void* stream);
+
+/* ---------------------------------------------------------------- a5: kernel prediction
+ * U-Net (2 x (3x3 conv + ReLU) per level, 2x2 average pool down, nearest-2x up + concat
+ * [up, skip]) with 1x1 heads: logits[l] [N, H>>l, W>>l, kstride[l]] in logit_dtype (F32 or
+ * the net's dtype) for l < n_heads.  H, W divisible by 8. */
+size_t aps_kernel_predict_workspace_size(const aps_net* net, int N, int H, int W);
+int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W, int C,
+                       int n_heads, void* const* logits, int logit_dtype, const int* kstride,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- a6-a9: reconstruction
+ * Logits of level l: [N, H_l, W_l, kstride_l] (float32 or bf16; kstride_l a multiple of 4
+ * for float32 and of 8 for bf16, >= the level's channel count K_l), channel blocks in order
+ * [kd: KD*KD | ku: KU*KU if l < levels-1 | kt: KT*KT if l == 0 and prev != NULL], each block
+ * row-major over (dy, dx) in [-r, r]: channel (dy+r)*K + (dx+r) weights (x+dx, y+dy).
+ * One softmax per pixel over all blocks of its level (App. A eqs. app-softmax-mid/full),
+ * evaluated in float32.  All gathers clamp coordinates to the image edge.
+ *   G (eq. app-gather):   sum kd * L^l[x+dx, y+dy]
+ *   U (eq. app-upsample): KU = 3: sum ku * Lhat^{l+1}[x/2+dx, y/2+dy];
+ *                         KU = 2: sum ku[j*2+i] * Lhat^{l+1}[(x+i)/2, (y+j)/2]
+ *   T (eq. app-recon-full): sum kt * Wprev[x+dx, y+dy], Wprev = bilinear sample of prev at
+ *                         (x + mv.x, y + mv.y) with both taps edge-clamped; mv float32
+ *                         [N,H,W,2] backward motion in pixels.
+ * Compiled (KD, KU, KT): (5,3,3), (7,3,3), (5,2,5), (3,3,3). */
+
+/* Coarse-to-fine: Lhat^{L-1} = G; Lhat^l = G + U; out = Lhat^0 (+ T when prev != NULL). */
+size_t aps_denoise_pyramid_workspace_size(int N, int H, int W, int levels);
+int aps_denoise_pyramid(const float* const* L, const void* const* logits, int logit_dtype,
+                        const int* kstride, int levels, int KD, int KU, int KT,
+                        const float* prev, const float* mv, int N, int H, int W, float* out,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* accum_out += T with the level-0 joint softmax (ku block present iff has_upsample). */
+int aps_reproject(const float* prev, const float* mv, const void* logits0, int logit_dtype,
+                  int kstride, int KD, int KU, int KT, int has_upsample, int N, int H, int W,
+                  float* accum_out, void* stream);
+
+/* accum_out += U(coarse) with the level's joint softmax (kt block present iff has_temporal);
+ * H, W are the fine sizes, coarse is [N, H/2, W/2]. */
+int aps_upsample(const float* coarse, const void* logits, int logit_dtype, int kstride, int KD,
+                 int KU, int KT, int has_temporal, int N, int H, int W, float* accum_out,
+                 void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APS_H */

@@ -1,0 +1,79 @@
+"""ctypes loader of libaps.so: argument types only, no computation."""
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaps.so")
+
+APS_F32, APS_BF16 = 0, 1
+APS_HARD, APS_RELAXED = 0, 1
+APS_FEAT_SAMPLER, APS_FEAT_KERNEL = 0, 1
+APS_CONV_DIRECT, APS_CONV_POOL2, APS_CONV_UP2_CAT = 0, 1, 2
+APS_MAX_LEVELS = 5
+APS_MAX_NET_LAYERS = 20
+APS_STATUS_COUNT_OVERFLOW, APS_STATUS_NONFINITE, APS_STATUS_CAPACITY = 1, 2, 4
+
+
+class ConvLayer(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("b", C.c_void_p), ("cin", C.c_int), ("cout", C.c_int),
+                ("ksize", C.c_int), ("relu", C.c_int)]
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int), ("dtype", C.c_int),
+                ("layer", ConvLayer * APS_MAX_NET_LAYERS)]
+
+
+P, I, I64, U64, U32, F, SZ = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_uint32, C.c_float, C.c_size_t
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "aps_version": (I, []),
+    "aps_status_string": (C.c_char_p, [I]),
+    "aps_conv_packed_elems": (SZ, [I, I, I]),
+    "aps_conv_pack_weights": (I, [P, I, I, I, I, P, P]),
+    "aps_conv2d_fwd": (I, [P, P, I, I, I, I, I, I, P, P, I, I, I, I, P, I, I, P]),
+    "aps_normalize_workspace_size": (SZ, [I, I, I]),
+    "aps_normalize_density": (I, [P, I, I, I, F, F, P, P, SZ, P, P]),
+    "aps_density_predict_workspace_size": (SZ, [I, I, I, I, I]),
+    "aps_density_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, F, F, P, P, P, SZ, P, P]),
+    "aps_sample_mask_workspace_size": (SZ, [I, I, I]),
+    "aps_sample_mask": (I, [P, I, I, I, U64, U32, P, P, P, I64, P, P, P, SZ, P, P]),
+    "aps_fixture_render": (I, [P, I, P, P, I, I, I, I64, P, P]),
+    "aps_scatter_samples": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P]),
+    "aps_assemble_features": (I, [I, P, P, P, P, P, I, I, I, I, I, P, P]),
+    "aps_kernel_predict_workspace_size": (SZ, [C.POINTER(NetDesc), I, I, I]),
+    "aps_kernel_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, I, P, I, P, P, SZ, P]),
+    "aps_denoise_pyramid_workspace_size": (SZ, [I, I, I, I]),
+    "aps_denoise_pyramid": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, P, P, SZ, P]),
+    "aps_reproject": (I, [P, P, P, I, I, I, I, I, I, I, I, I, P, P]),
+    "aps_upsample": (I, [P, P, I, I, I, I, I, I, I, I, I, P, P]),
+}
+
+_lib = None
+
+
+def load():
+    """The loaded library; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2602_08642_amd.build` (hipcc, gfx950)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class ApsError(RuntimeError):
+    pass
+
+
+def check(status: int, what: str = ""):
+    if status != 0:
+        msg = load().aps_status_string(status).decode()
+        raise ApsError(f"{what}: aps status {status} ({msg})")

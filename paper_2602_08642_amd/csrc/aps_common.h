@@ -1,0 +1,102 @@
+// Internal device helpers shared by the gfx950 kernels of libaps (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/aps.h"
+
+#define APS_HIP_TRY(expr)                                   \
+  do {                                                      \
+    if ((expr) != hipSuccess) return APS_ERR_HIP;           \
+  } while (0)
+
+#define APS_LAUNCH_CHECK()                                  \
+  do {                                                      \
+    if (hipGetLastError() != hipSuccess) return APS_ERR_HIP; \
+  } while (0)
+
+namespace aps {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+struct LevelPtrs {
+  float4* p[APS_MAX_LEVELS];
+};
+
+static inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- bfloat16 <-> float (round to nearest even, NaN kept quiet) ------------------------
+__device__ __host__ inline uint16_t f2bf(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __host__ inline float bf2f(uint16_t h) {
+  return __builtin_bit_cast(float, ((uint32_t)h) << 16);
+}
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) --------------------------------------------
+__device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// u in [0, 1 - 2^-24]: top 24 bits of word 0 for counter (pixel, frame, stream 0, 0).
+__device__ inline float uniform24(uint64_t seed, uint32_t pixel, uint32_t frame) {
+  const uint4 r = philox4x32_10(make_uint4(pixel, frame, 0u, 0u), (uint32_t)seed,
+                                (uint32_t)(seed >> 32));
+  return (float)(r.x >> 8) * 0x1p-24f;
+}
+
+// ---- wave / block reductions (wave64) -------------------------------------------------
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_isum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// inclusive prefix sum within a wave64
+__device__ inline int wave_iscan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ inline void status_or(uint32_t* st, uint32_t bits) {
+  if (st) atomicOr(st, bits);
+}
+
+template <typename T> struct Ld;
+template <> struct Ld<float> {
+  static __device__ inline float get(const float* p, size_t i) { return p[i]; }
+};
+template <> struct Ld<uint16_t> {
+  static __device__ inline float get(const uint16_t* p, size_t i) { return bf2f(p[i]); }
+};
+
+}  // namespace aps

@@ -1,0 +1,148 @@
+// Network entry points: the sampler CNN followed by budget normalisation (Sec. 3,
+// Overview), and the kernel-predictor U-Net producing per-level kernel logits (App. A,
+// kernel prediction).  Every layer runs in the MFMA convolution of conv.hip; this file
+// only sequences launches on the caller's stream and carves the caller's workspace.
+#include "aps_common.h"
+
+using namespace aps;
+
+namespace {
+
+size_t esize(int dtype) { return dtype == APS_BF16 ? 2 : 4; }
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int conv(const aps_conv_layer& L, const void* x, const void* x2, int N, int H, int W, int Cx,
+         int C2, int mode, int dtype, void* y, int ldy, int y_dtype, void* stream) {
+  if (!L.w || !L.b) return APS_ERR_NULL;
+  if (L.cin != Cx + C2) return APS_ERR_SHAPE;
+  return aps_conv2d_fwd(x, x2, N, H, W, Cx, C2, mode, L.w, L.b, L.cout, L.ksize, L.relu, dtype,
+                        y, ldy, y_dtype, stream);
+}
+
+#define APS_TRY(expr)            \
+  do {                           \
+    const int _r = (expr);       \
+    if (_r != APS_OK) return _r; \
+  } while (0)
+
+const int kUnetConvs = 14;
+
+}  // namespace
+
+extern "C" {
+
+size_t aps_density_predict_workspace_size(int N, int H, int W, int width, int dtype) {
+  return 2 * align256((size_t)N * H * W * width * esize(dtype)) + align256((size_t)N * H * W * 4) +
+         align256(aps_normalize_workspace_size(N, H, W));
+}
+
+int aps_density_predict(const aps_net* net, const void* feat, int N, int H, int W, int C,
+                        float budget_spp, float uniform_frac, float* z_out, float* s_out,
+                        void* ws, size_t ws_bytes, uint32_t* dev_status, void* stream) {
+  if (!net) return APS_ERR_NULL;
+  if (net->n_layers != 3) return APS_ERR_SHAPE;
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!feat || !s_out) return APS_ERR_NULL;
+  const int dt = net->dtype;
+  if (dt != APS_F32 && dt != APS_BF16) return APS_ERR_UNSUPPORTED;
+  const aps_conv_layer* L = net->layer;
+  const int width = L[0].cout;
+  if (L[1].cin != width || L[2].cin != L[1].cout || L[2].cout != 1 || L[0].cin != C)
+    return APS_ERR_SHAPE;
+  const int wmax = width > L[1].cout ? width : L[1].cout;
+  if (!ws || ws_bytes < aps_density_predict_workspace_size(N, H, W, wmax, dt)) return APS_ERR_WORKSPACE;
+  char* p = static_cast<char*>(ws);
+  void* t0 = p;
+  p += align256((size_t)N * H * W * wmax * esize(dt));
+  void* t1 = p;
+  p += align256((size_t)N * H * W * wmax * esize(dt));
+  float* z = reinterpret_cast<float*>(p);
+  p += align256((size_t)N * H * W * 4);
+  if (z_out) z = z_out;
+  APS_TRY(conv(L[0], feat, nullptr, N, H, W, C, 0, APS_CONV_DIRECT, dt, t0, width, dt, stream));
+  APS_TRY(conv(L[1], t0, nullptr, N, H, W, width, 0, APS_CONV_DIRECT, dt, t1, L[1].cout, dt, stream));
+  APS_TRY(conv(L[2], t1, nullptr, N, H, W, L[1].cout, 0, APS_CONV_DIRECT, dt, z, 1, APS_F32, stream));
+  return aps_normalize_density(z, N, H, W, budget_spp, uniform_frac, s_out, p,
+                               aps_normalize_workspace_size(N, H, W), dev_status, stream);
+}
+
+size_t aps_kernel_predict_workspace_size(const aps_net* net, int N, int H, int W) {
+  if (!net || net->n_layers < kUnetConvs + 1) return 0;
+  const aps_conv_layer* L = net->layer;
+  const size_t px = (size_t)N * H * W, e = esize(net->dtype);
+  const size_t c0 = L[1].cout, c1 = L[3].cout, c2 = L[5].cout, c3 = L[7].cout;
+  size_t b = 0;
+  b += align256(px * c0 * e);            // e0
+  b += align256(px / 4 * c1 * e);        // e1
+  b += align256(px / 16 * c2 * e);       // e2
+  b += align256(px / 64 * c3 * e);       // e3
+  b += align256(px / 16 * c2 * e);       // d2
+  b += align256(px / 4 * c1 * e);        // d1
+  b += align256(px * c0 * e);            // d0
+  size_t t = px * c0;                    // scratch for the first conv of each pair
+  if (px / 4 * c1 > t) t = px / 4 * c1;
+  if (px / 16 * c2 > t) t = px / 16 * c2;
+  if (px / 64 * c3 > t) t = px / 64 * c3;
+  b += align256(t * e);
+  return b;
+}
+
+int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W, int C,
+                       int n_heads, void* const* logits, int logit_dtype, const int* kstride,
+                       void* ws, size_t ws_bytes, void* stream) {
+  if (!net) return APS_ERR_NULL;
+  if (n_heads < 1 || n_heads > 4 || net->n_layers != kUnetConvs + n_heads) return APS_ERR_SHAPE;
+  if (N < 0 || H < 0 || W < 0 || H % 8 || W % 8) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!feat || !logits || !kstride) return APS_ERR_NULL;
+  const int dt = net->dtype;
+  if (dt != APS_F32 && dt != APS_BF16) return APS_ERR_UNSUPPORTED;
+  if (logit_dtype != APS_F32 && logit_dtype != dt) return APS_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < aps_kernel_predict_workspace_size(net, N, H, W)) return APS_ERR_WORKSPACE;
+  const aps_conv_layer* L = net->layer;
+  const int c0 = L[1].cout, c1 = L[3].cout, c2 = L[5].cout, c3 = L[7].cout;
+  const size_t px = (size_t)N * H * W, e = esize(dt);
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) {
+    void* r = p;
+    p += align256(bytes);
+    return r;
+  };
+  void* e0 = take(px * c0 * e);
+  void* e1 = take(px / 4 * c1 * e);
+  void* e2 = take(px / 16 * c2 * e);
+  void* e3 = take(px / 64 * c3 * e);
+  void* d2 = take(px / 16 * c2 * e);
+  void* d1 = take(px / 4 * c1 * e);
+  void* d0 = take(px * c0 * e);
+  void* t = p;
+  const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
+  // encoder
+  APS_TRY(conv(L[0], feat, nullptr, N, H, W, C, 0, APS_CONV_DIRECT, dt, t, L[0].cout, dt, stream));
+  APS_TRY(conv(L[1], t, nullptr, N, H, W, L[0].cout, 0, APS_CONV_DIRECT, dt, e0, c0, dt, stream));
+  APS_TRY(conv(L[2], e0, nullptr, N, H1, W1, c0, 0, APS_CONV_POOL2, dt, t, L[2].cout, dt, stream));
+  APS_TRY(conv(L[3], t, nullptr, N, H1, W1, L[2].cout, 0, APS_CONV_DIRECT, dt, e1, c1, dt, stream));
+  APS_TRY(conv(L[4], e1, nullptr, N, H2, W2, c1, 0, APS_CONV_POOL2, dt, t, L[4].cout, dt, stream));
+  APS_TRY(conv(L[5], t, nullptr, N, H2, W2, L[4].cout, 0, APS_CONV_DIRECT, dt, e2, c2, dt, stream));
+  APS_TRY(conv(L[6], e2, nullptr, N, H3, W3, c2, 0, APS_CONV_POOL2, dt, t, L[6].cout, dt, stream));
+  APS_TRY(conv(L[7], t, nullptr, N, H3, W3, L[6].cout, 0, APS_CONV_DIRECT, dt, e3, c3, dt, stream));
+  // decoder: concat [nearest-2x(deeper), skip]
+  APS_TRY(conv(L[8], e3, e2, N, H2, W2, c3, c2, APS_CONV_UP2_CAT, dt, t, L[8].cout, dt, stream));
+  APS_TRY(conv(L[9], t, nullptr, N, H2, W2, L[8].cout, 0, APS_CONV_DIRECT, dt, d2, c2, dt, stream));
+  APS_TRY(conv(L[10], d2, e1, N, H1, W1, c2, c1, APS_CONV_UP2_CAT, dt, t, L[10].cout, dt, stream));
+  APS_TRY(conv(L[11], t, nullptr, N, H1, W1, L[10].cout, 0, APS_CONV_DIRECT, dt, d1, c1, dt, stream));
+  APS_TRY(conv(L[12], d1, e0, N, H, W, c1, c0, APS_CONV_UP2_CAT, dt, t, L[12].cout, dt, stream));
+  APS_TRY(conv(L[13], t, nullptr, N, H, W, L[12].cout, 0, APS_CONV_DIRECT, dt, d0, c0, dt, stream));
+  // 1x1 heads
+  const void* feats[4] = {d0, d1, d2, e3};
+  const int fc[4] = {c0, c1, c2, c3};
+  for (int l = 0; l < n_heads; ++l) {
+    if (!logits[l]) return APS_ERR_NULL;
+    APS_TRY(conv(L[kUnetConvs + l], feats[l], nullptr, N, H >> l, W >> l, fc[l], 0,
+                 APS_CONV_DIRECT, dt, logits[l], kstride[l], logit_dtype, stream));
+  }
+  return APS_OK;
+}
+
+}  // extern "C"

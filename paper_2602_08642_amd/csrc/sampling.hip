@@ -1,0 +1,501 @@
+// Sampling stages of the per-frame path on gfx950:
+//   budget normalisation z -> s            (Sec. 3, Overview)
+//   stochastic-rounding mask s, u -> counts, offsets, compact sample list
+//                                          (Sec. 4.2, eq. holdout)
+//   s-normalised scatter + pyramid         (Sec. 4.2 eq. stoch_rnoisy, Sec. 4.3 eqs.
+//                                           relaxed_holdout / h_factor, App. A eq. app-pyramid)
+//   renderer stand-in and feature assembly (inputs of the two networks)
+#include "aps_common.h"
+
+using namespace aps;
+
+namespace {
+
+constexpr int kNormElems = 2048;  // pixels per block of the softmax partial reductions
+constexpr int kMaskBlock = 256;   // pixels per block of the sample-list offsets
+
+// ------------------------------------------------------------------ normalisation
+// Partial (max, sum exp(z - max)) over kNormElems pixels of one image; fixed partition,
+// fixed reduction tree: deterministic.
+__global__ __launch_bounds__(256) void k_norm_partial(const float* __restrict__ z, int npx,
+                                                      int nb, float2* __restrict__ part) {
+  const int n = blockIdx.y, b = blockIdx.x;
+  const float* zi = z + (size_t)n * npx;
+  const int base = b * kNormElems;
+  float v[kNormElems / 256];
+  float m = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < kNormElems / 256; ++k) {
+    const int i = base + k * 256 + threadIdx.x;
+    v[k] = i < npx ? zi[i] : -INFINITY;
+    m = fmaxf(m, v[k]);
+  }
+  __shared__ float sm[4];
+  __shared__ float ss[4];
+  m = wave_max(m);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[w] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
+  float e = 0.f;
+#pragma unroll
+  for (int k = 0; k < kNormElems / 256; ++k) e += (v[k] == -INFINITY) ? 0.f : expf(v[k] - m);
+  e = wave_sum(e);
+  if ((threadIdx.x & 63) == 0) ss[w] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)n * nb + b] = make_float2(m, (ss[0] + ss[1]) + (ss[2] + ss[3]));
+}
+
+// One block per image: combine partials into (max, sum) with a fixed order.
+__global__ __launch_bounds__(256) void k_norm_combine(const float2* __restrict__ part, int nb,
+                                                      float2* __restrict__ stats) {
+  const int n = blockIdx.x;
+  const float2* p = part + (size_t)n * nb;
+  float m = -INFINITY;
+  for (int b = threadIdx.x; b < nb; b += 256) m = fmaxf(m, p[b].x);
+  __shared__ float red[4];
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  __syncthreads();
+  float e = 0.f;
+  for (int b = threadIdx.x; b < nb; b += 256) e += p[b].y * expf(p[b].x - m);
+  e = wave_sum(e);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) stats[n] = make_float2(m, (red[0] + red[1]) + (red[2] + red[3]));
+}
+
+// s = f*B + (1-f)*B*Npx * exp(z - max) / sum
+__global__ __launch_bounds__(256) void k_norm_apply(const float* __restrict__ z, int npx,
+                                                    const float2* __restrict__ stats, float c0,
+                                                    float c1, float* __restrict__ s,
+                                                    uint32_t* st) {
+  const int n = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= npx) return;
+  const float2 ms = stats[n];
+  const float zi = z[(size_t)n * npx + i];
+  const float v = c0 + c1 * (expf(zi - ms.x) / ms.y);
+  if (!isfinite(v)) status_or(st, APS_STATUS_NONFINITE);
+  s[(size_t)n * npx + i] = v;
+}
+
+// ------------------------------------------------------------------ sample mask
+__global__ __launch_bounds__(kMaskBlock) void k_mask_count(const float* __restrict__ s,
+                                                           int npix, uint64_t seed, uint32_t frame,
+                                                           uint8_t* __restrict__ count,
+                                                           float* __restrict__ p_out,
+                                                           int32_t* __restrict__ block_sum,
+                                                           uint32_t* st) {
+  const int i = blockIdx.x * kMaskBlock + threadIdx.x;
+  int c = 0;
+  if (i < npix) {
+    const float si = s[i];
+    float p = 0.f;
+    if (!(si >= 0.f) || !isfinite(si)) {
+      status_or(st, APS_STATUS_NONFINITE);
+    } else {
+      const float fl = floorf(si);
+      p = si - fl;  // exact in binary32
+      const float u = uniform24(seed, (uint32_t)i, frame);
+      if (fl > 254.f) {
+        status_or(st, APS_STATUS_COUNT_OVERFLOW);
+        c = 255;
+      } else {
+        c = (int)fl + (u < p ? 1 : 0);
+        if (c > 255) {
+          status_or(st, APS_STATUS_COUNT_OVERFLOW);
+          c = 255;
+        }
+      }
+    }
+    count[i] = (uint8_t)c;
+    if (p_out) p_out[i] = p;
+  }
+  __shared__ int red[kMaskBlock / 64];
+  const int ws = wave_isum(c);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
+  __syncthreads();
+  if (threadIdx.x == 0) block_sum[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Single block: exclusive scan of the block sums, and the total.
+__global__ __launch_bounds__(1024) void k_mask_scan(const int32_t* __restrict__ block_sum, int nb,
+                                                    int32_t* __restrict__ block_off,
+                                                    int32_t* __restrict__ total) {
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = t * per, b1 = min(b0 + per, nb);
+  int local = 0;
+  for (int b = b0; b < b1; ++b) local += block_sum[b];
+  __shared__ int wsum[16];
+  const int incl = wave_iscan(local);
+  if ((t & 63) == 63) wsum[t >> 6] = incl;
+  __syncthreads();
+  if (t < 64) {
+    const int v = t < 16 ? wsum[t] : 0;
+    const int sc = wave_iscan(v);
+    if (t < 16) wsum[t] = sc - v;  // exclusive wave offsets
+  }
+  __syncthreads();
+  int run = wsum[t >> 6] + incl - local;
+  for (int b = b0; b < b1; ++b) {
+    block_off[b] = run;
+    run += block_sum[b];
+  }
+  if (t == 1023) *total = run;
+}
+
+__global__ __launch_bounds__(kMaskBlock) void k_mask_compact(const uint8_t* __restrict__ count,
+                                                             int npix,
+                                                             const int32_t* __restrict__ block_off,
+                                                             int32_t* __restrict__ pixel_offset,
+                                                             int32_t* __restrict__ sample_pixel,
+                                                             int64_t capacity, uint32_t* st) {
+  const int i = blockIdx.x * kMaskBlock + threadIdx.x;
+  const int c = i < npix ? (int)count[i] : 0;
+  __shared__ int wsum[kMaskBlock / 64];
+  const int incl = wave_iscan(c);
+  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < (threadIdx.x >> 6); ++w) before += wsum[w];
+  if (i >= npix) return;
+  const int off = block_off[blockIdx.x] + before + incl - c;
+  pixel_offset[i] = off;
+  for (int j = 0; j < c; ++j) {
+    if ((int64_t)off + j < capacity) sample_pixel[off + j] = i;
+    else status_or(st, APS_STATUS_CAPACITY);
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+// ------------------------------------------------------------------ renderer stand-in
+__global__ __launch_bounds__(256) void k_fixture_render(const float4* __restrict__ pool, int J,
+                                                        const uint8_t* __restrict__ count,
+                                                        const int32_t* __restrict__ pixel_offset,
+                                                        int npix, int64_t capacity,
+                                                        float4* __restrict__ samples) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= npix) return;
+  const int c = count[i];
+  const int off = pixel_offset[i];
+  for (int j = 0; j < c; ++j)
+    if ((int64_t)off + j < capacity) samples[off + j] = pool[(size_t)i * J + (j % J)];
+}
+
+// ------------------------------------------------------------------ scatter + pyramid
+// One 16x16 tile of level-0 pixels per block.  Level 0 is the s-normalised estimate,
+// levels 1.. are 2x2 means of the level above, reduced in LDS (= 2^l x 2^l block means).
+__global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ s,
+                                                 const uint8_t* __restrict__ count,
+                                                 const int32_t* __restrict__ pixel_offset,
+                                                 const float4* __restrict__ samples,
+                                                 int64_t n_samples, int H, int W, int levels, int relaxed, float lam, float hfac,
+                                                 uint64_t seed, uint32_t frame, LevelPtrs Lp) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int x = blockIdx.x * 16 + tx, y = blockIdx.y * 16 + ty, n = blockIdx.z;
+  __shared__ float4 tile[16][17];
+  float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
+  const bool in = x < W && y < H;
+  if (in) {
+    const size_t i = ((size_t)n * H + y) * W + x;
+    const float si = s[i];
+    const int c = count[i];
+    const int off = pixel_offset[i];
+    const float fl = floorf(si);
+    const int nb = min(c, (int)fl);
+    // samples past the caller's buffer (a mask that overflowed its capacity) read as 0
+    const int lim = (int)min((int64_t)c, max((int64_t)0, n_samples - off));
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    for (int j = 0; j < min(nb, lim); ++j) {
+      const float4 v = samples[off + j];
+      ax += v.x;
+      ay += v.y;
+      az += v.z;
+    }
+    if (c > nb && nb < lim) {  // the holdout sample was taken (u < p)
+      const float4 r = samples[off + nb];
+      float w = 1.f;
+      if (relaxed) {
+        const float p = si - fl;
+        const float u = uniform24(seed, (uint32_t)i, frame);
+        w = hfac * fminf(fmaxf(lam * (p - u) / p, 0.f), 1.f);
+      }
+      ax += w * r.x;
+      ay += w * r.y;
+      az += w * r.z;
+    }
+    if (si > 0.f) L = make_float4(ax / si, ay / si, az / si, 0.f);
+    Lp.p[0][i] = L;
+  }
+  tile[ty][tx] = L;
+  int Hl = H, Wl = W;
+  for (int l = 1; l < levels; ++l) {
+    __syncthreads();
+    const int t = 16 >> l;
+    Hl >>= 1;
+    Wl >>= 1;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tx < t && ty < t) {
+      const float4 a = tile[2 * ty][2 * tx], b = tile[2 * ty][2 * tx + 1];
+      const float4 c = tile[2 * ty + 1][2 * tx], d = tile[2 * ty + 1][2 * tx + 1];
+      v = make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
+                      ((a.z + b.z) + (c.z + d.z)) * 0.25f, 0.f);
+    }
+    __syncthreads();
+    if (tx < t && ty < t) {
+      tile[ty][tx] = v;
+      const int xl = blockIdx.x * t + tx, yl = blockIdx.y * t + ty;
+      if (xl < Wl && yl < Hl) Lp.p[l][((size_t)n * Hl + yl) * Wl + xl] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ feature assembly
+__device__ inline float slog1p(float v) { return copysignf(log1pf(fabsf(v)), v); }
+
+// Evaluation tonemapper of the feedback loop (Sec. 5): log, curve tau(x; 0.5, 0.5) with
+// contrast 0.4, exposure 0, saturation 1, then the sRGB transfer function.
+__device__ inline float tau_eval(float x) {
+  const float s = 0.5f, h = 0.5f;
+  if (x < s - 1.f) return 0.5f * s * expf((x + 1.f - s) / s);
+  if (x < 1.f - h) return 0.5f * (1.f + x);
+  return 1.f - 0.5f * h * expf(-(x + h - 1.f) / h);
+}
+__device__ inline float srgb(float v) {
+  v = fminf(fmaxf(v, 0.f), 1.f);
+  return v <= 0.0031308f ? 12.92f * v : 1.055f * powf(v, 1.f / 2.4f) - 0.055f;
+}
+__device__ inline float tonemap_eval(float L) {
+  return srgb(tau_eval(0.4f * logf(fmaxf(L, 0.f) + 1e-4f)));
+}
+
+// Bilinear sample of prev at (x + mv.x, y + mv.y), both taps clamped to the edge; the
+// integer cell comes from floor(mv) so the fractional weights are exact.
+__device__ inline float4 warp_sample(const float4* __restrict__ prev, int H, int W, int n, int x,
+                                     int y, float2 mv) {
+  const float fxf = floorf(mv.x), fyf = floorf(mv.y);
+  const float fx = mv.x - fxf, fy = mv.y - fyf;
+  const int x0 = x + (int)fxf, y0 = y + (int)fyf;
+  const int xa = min(max(x0, 0), W - 1), xb = min(max(x0 + 1, 0), W - 1);
+  const int ya = min(max(y0, 0), H - 1), yb = min(max(y0 + 1, 0), H - 1);
+  const float4* P = prev + (size_t)n * H * W;
+  const float4 a = P[(size_t)ya * W + xa], b = P[(size_t)ya * W + xb];
+  const float4 c = P[(size_t)yb * W + xa], d = P[(size_t)yb * W + xb];
+  const float gx = 1.f - fx, gy = 1.f - fy;
+  return make_float4(gy * (gx * a.x + fx * b.x) + fy * (gx * c.x + fx * d.x),
+                     gy * (gx * a.y + fx * b.y) + fy * (gx * c.y + fx * d.y),
+                     gy * (gx * a.z + fx * b.z) + fy * (gx * c.z + fx * d.z), 0.f);
+}
+
+__device__ inline float mv_valid(int H, int W, int x, int y, float2 mv) {
+  const float px = (float)x + mv.x, py = (float)y + mv.y;
+  return (px >= -0.5f && px <= (float)W - 0.5f && py >= -0.5f && py <= (float)H - 0.5f) ? 1.f : 0.f;
+}
+
+template <typename T>
+__device__ inline void store_feat(T* out, int c, float v);
+template <>
+__device__ inline void store_feat<float>(float* out, int c, float v) { out[c] = v; }
+template <>
+__device__ inline void store_feat<uint16_t>(uint16_t* out, int c, float v) { out[c] = f2bf(v); }
+
+// kind 0 (sampler input):   aux[0..6], then (temporal) tonemap(W prev) 3, valid 1; zero pad.
+// kind 1 (kernel predictor): aux[0..6], slog1p(L0) 3, s 1, then (temporal) slog1p(W prev) 3,
+//                            valid 1; zero pad.
+template <typename T>
+__global__ __launch_bounds__(256) void k_features(int kind, const float* __restrict__ aux,
+                                                  const float4* __restrict__ L0,
+                                                  const float* __restrict__ s,
+                                                  const float4* __restrict__ prev,
+                                                  const float2* __restrict__ mv, int N, int H,
+                                                  int W, int C, T* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t npix = (size_t)N * H * W;
+  if (i >= npix) return;
+  const int x = (int)(i % W), y = (int)((i / W) % H), n = (int)(i / ((size_t)W * H));
+  float f[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) f[c] = 0.f;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) f[c] = aux[i * 8 + c];
+  int o = 7;
+  if (kind == 1) {
+    const float4 l = L0[i];
+    f[7] = slog1p(l.x);
+    f[8] = slog1p(l.y);
+    f[9] = slog1p(l.z);
+    f[10] = s[i];
+    o = 11;
+  }
+  if (prev) {
+    const float2 m = mv[i];
+    const float4 w = warp_sample(prev, H, W, n, x, y, m);
+    if (kind == 0) {
+      f[o] = tonemap_eval(w.x);
+      f[o + 1] = tonemap_eval(w.y);
+      f[o + 2] = tonemap_eval(w.z);
+    } else {
+      f[o] = slog1p(w.x);
+      f[o + 1] = slog1p(w.y);
+      f[o + 2] = slog1p(w.z);
+    }
+    f[o + 3] = mv_valid(H, W, x, y, m);
+  }
+  T* dst = out + i * C;
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    if (c < C) store_feat<T>(dst, c, f[c]);
+}
+
+}  // namespace
+
+// ======================================================================== C ABI
+extern "C" {
+
+size_t aps_normalize_workspace_size(int N, int H, int W) {
+  const int npx = H * W;
+  const int nb = (npx + kNormElems - 1) / kNormElems;
+  return (size_t)N * nb * sizeof(float2) + (size_t)N * sizeof(float2) + 256;
+}
+
+int aps_normalize_density(const float* z, int N, int H, int W, float budget_spp,
+                          float uniform_frac, float* s_out, void* ws, size_t ws_bytes,
+                          uint32_t* dev_status, void* stream) {
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!z || !s_out) return APS_ERR_NULL;
+  if (!(budget_spp > 0.f) || !(uniform_frac >= 0.f && uniform_frac <= 1.f)) return APS_ERR_ARG;
+  if ((size_t)H * W > 0x7fffffffull) return APS_ERR_SHAPE;
+  if (ws_bytes < aps_normalize_workspace_size(N, H, W) || !ws) return APS_ERR_WORKSPACE;
+  const int npx = H * W;
+  const int nb = (npx + kNormElems - 1) / kNormElems;
+  float2* part = static_cast<float2*>(ws);
+  float2* stats = part + (size_t)N * nb;
+  hipStream_t st = as_stream(stream);
+  k_norm_partial<<<dim3(nb, N), 256, 0, st>>>(z, npx, nb, part);
+  k_norm_combine<<<N, 256, 0, st>>>(part, nb, stats);
+  const float c0 = uniform_frac * budget_spp;
+  const float c1 = (1.f - uniform_frac) * budget_spp * (float)npx;
+  k_norm_apply<<<dim3((npx + 255) / 256, N), 256, 0, st>>>(z, npx, stats, c0, c1, s_out,
+                                                           dev_status);
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+size_t aps_sample_mask_workspace_size(int N, int H, int W) {
+  const size_t npix = (size_t)N * H * W;
+  const size_t nb = (npix + kMaskBlock - 1) / kMaskBlock;
+  return 2 * nb * sizeof(int32_t) + 256;
+}
+
+int aps_sample_mask(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                    uint8_t* count, int32_t* pixel_offset, int32_t* sample_pixel,
+                    int64_t capacity, int32_t* total, float* p_out, void* ws, size_t ws_bytes,
+                    uint32_t* dev_status, void* stream) {
+  if (N < 0 || H < 0 || W < 0 || capacity < 0) return APS_ERR_SHAPE;
+  const size_t npix = (size_t)N * H * W;
+  if (npix > 0x7fffffffull) return APS_ERR_SHAPE;
+  if (!total) return APS_ERR_NULL;
+  hipStream_t st = as_stream(stream);
+  if (npix == 0) {  // a kernel, not a memset node: safe under stream capture
+    k_zero_i32<<<1, 64, 0, st>>>(total);
+    APS_LAUNCH_CHECK();
+    return APS_OK;
+  }
+  if (!s || !count || !pixel_offset || (!sample_pixel && capacity > 0)) return APS_ERR_NULL;
+  if (!ws || ws_bytes < aps_sample_mask_workspace_size(N, H, W)) return APS_ERR_WORKSPACE;
+  const int nb = (int)((npix + kMaskBlock - 1) / kMaskBlock);
+  int32_t* bsum = static_cast<int32_t*>(ws);
+  int32_t* boff = bsum + nb;
+  k_mask_count<<<nb, kMaskBlock, 0, st>>>(s, (int)npix, seed, frame, count, p_out, bsum,
+                                          dev_status);
+  k_mask_scan<<<1, 1024, 0, st>>>(bsum, nb, boff, total);
+  k_mask_compact<<<nb, kMaskBlock, 0, st>>>(count, (int)npix, boff, pixel_offset, sample_pixel,
+                                            capacity, dev_status);
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+int aps_fixture_render(const float* pool, int J, const uint8_t* count,
+                       const int32_t* pixel_offset, int N, int H, int W, int64_t capacity,
+                       float* samples, void* stream) {
+  if (J <= 0 || N < 0 || H < 0 || W < 0 || capacity < 0) return APS_ERR_SHAPE;
+  const size_t npix = (size_t)N * H * W;
+  if (npix == 0) return APS_OK;
+  if (!pool || !count || !pixel_offset || (!samples && capacity > 0)) return APS_ERR_NULL;
+  if (npix > 0x7fffffffull) return APS_ERR_SHAPE;
+  k_fixture_render<<<(int)((npix + 255) / 256), 256, 0, as_stream(stream)>>>(
+      reinterpret_cast<const float4*>(pool), J, count, pixel_offset, (int)npix, capacity,
+      reinterpret_cast<float4*>(samples));
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+int aps_scatter_samples(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                        const float* samples, int64_t n_samples, int N, int H, int W, int levels,
+                        int mode,
+                        float lambda, uint64_t seed, uint32_t frame, float* const* L,
+                        void* stream) {
+  if (n_samples < 0) return APS_ERR_SHAPE;
+  if (levels < 1 || levels > APS_MAX_LEVELS) return APS_ERR_UNSUPPORTED;
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if (mode != APS_HARD && mode != APS_RELAXED) return APS_ERR_ARG;
+  if (mode == APS_RELAXED && !(lambda >= 1.f)) return APS_ERR_ARG;
+  const int div = 1 << (levels - 1);
+  if (H % div || W % div) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W > 0x7fffffffull) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!s || !count || !pixel_offset || !L || (!samples && n_samples > 0)) return APS_ERR_NULL;
+  LevelPtrs lp{};
+  for (int l = 0; l < levels; ++l) {
+    if (!L[l]) return APS_ERR_NULL;
+    lp.p[l] = reinterpret_cast<float4*>(L[l]);
+  }
+  const float hfac = 2.f * lambda / (2.f * lambda - 1.f);
+  dim3 grid((W + 15) / 16, (H + 15) / 16, N);
+  k_scatter<<<grid, 256, 0, as_stream(stream)>>>(s, count, pixel_offset,
+                                                 reinterpret_cast<const float4*>(samples),
+                                                 n_samples, H, W, levels, mode == APS_RELAXED, lambda, hfac, seed,
+                                                 frame, lp);
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+int aps_assemble_features(int kind, const float* aux, const float* L0, const float* s,
+                          const float* prev, const float* mv, int N, int H, int W, int C,
+                          int out_dtype, void* out, void* stream) {
+  if (kind != APS_FEAT_SAMPLER && kind != APS_FEAT_KERNEL) return APS_ERR_ARG;
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!aux || !out) return APS_ERR_NULL;
+  if (kind == APS_FEAT_KERNEL && (!L0 || !s)) return APS_ERR_NULL;
+  if (prev && !mv) return APS_ERR_NULL;
+  const int need = (kind == APS_FEAT_KERNEL ? 11 : 7) + (prev ? 4 : 0);
+  if (C < need || C > 16) return APS_ERR_SHAPE;
+  const size_t npix = (size_t)N * H * W;
+  if (npix == 0) return APS_OK;
+  const int blocks = (int)((npix + 255) / 256);
+  hipStream_t st = as_stream(stream);
+  const float4* L4 = reinterpret_cast<const float4*>(L0);
+  const float4* P4 = reinterpret_cast<const float4*>(prev);
+  const float2* M2 = reinterpret_cast<const float2*>(mv);
+  if (out_dtype == APS_F32)
+    k_features<float><<<blocks, 256, 0, st>>>(kind, aux, L4, s, P4, M2, N, H, W, C,
+                                              static_cast<float*>(out));
+  else if (out_dtype == APS_BF16)
+    k_features<uint16_t><<<blocks, 256, 0, st>>>(kind, aux, L4, s, P4, M2, N, H, W, C,
+                                                 static_cast<uint16_t*>(out));
+  else
+    return APS_ERR_UNSUPPORTED;
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+"""Torch-tensor wrappers of the libaps C ABI.
+
+Each function checks shapes and dtypes, allocates its outputs with torch (device memory
+only), and calls the library on the current HIP stream.  All arithmetic of the path runs
+in the library's kernels; nothing here computes on the data.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+_BF16, _F32 = torch.bfloat16, torch.float32
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dt(torch_dtype):
+    if torch_dtype == _F32:
+        return L.APS_F32
+    if torch_dtype == _BF16:
+        return L.APS_BF16
+    raise TypeError(f"unsupported dtype {torch_dtype}")
+
+
+def _tdt(aps_dtype):
+    return _F32 if aps_dtype == L.APS_F32 else _BF16
+
+
+def _need(t, name, dtype=None, dev=True):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if dev and not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t
+
+
+class _Workspace:
+    """Per-device scratch buffer that only grows (no allocation once warm)."""
+
+    def __init__(self):
+        self.buf = {}
+
+    def get(self, nbytes: int, device):
+        key = (device.index if device.index is not None else torch.cuda.current_device())
+        b = self.buf.get(key)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+            self.buf[key] = b
+        return b
+
+
+WS = _Workspace()
+
+
+def _status_tensor(device):
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+# ------------------------------------------------------------------ density (a1, a2)
+
+def normalize_density(z, budget: float, uniform_frac: float = 1.0 / 8.0, status=None):
+    _need(z, "z", _F32)
+    N, H, W = z.shape
+    s = torch.empty_like(z)
+    lib = L.load()
+    nb = lib.aps_normalize_workspace_size(N, H, W)
+    ws = WS.get(nb, z.device)
+    L.check(lib.aps_normalize_density(_p(z), N, H, W, budget, uniform_frac, _p(s), _p(ws), nb,
+                                      _p(status), _stream()), "normalize_density")
+    return s
+
+
+# ------------------------------------------------------------------ mask (a3)
+
+def sample_mask(s, seed: int, frame: int, capacity: int | None = None, want_p=False, status=None):
+    _need(s, "s", _F32)
+    N, H, W = s.shape
+    dev = s.device
+    npix = N * H * W
+    if capacity is None:
+        capacity = npix * 2
+    count = torch.empty((N, H, W), dtype=torch.uint8, device=dev)
+    poff = torch.empty((N, H, W), dtype=torch.int32, device=dev)
+    spix = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    total = torch.empty(1, dtype=torch.int32, device=dev)
+    p = torch.empty_like(s) if want_p else None
+    lib = L.load()
+    nb = lib.aps_sample_mask_workspace_size(N, H, W)
+    ws = WS.get(nb, dev)
+    L.check(lib.aps_sample_mask(_p(s), N, H, W, seed, frame, _p(count), _p(poff), _p(spix),
+                                capacity, _p(total), _p(p), _p(ws), nb, _p(status), _stream()),
+            "sample_mask")
+    return dict(count=count, pixel_offset=poff, sample_pixel=spix, total=total, p=p,
+                capacity=capacity)
+
+
+def fixture_render(pool, count, pixel_offset, capacity: int):
+    _need(pool, "pool", _F32)
+    N, H, W = count.shape
+    J = pool.shape[-2]
+    out = torch.empty((max(capacity, 1), 4), dtype=_F32, device=pool.device)
+    L.check(L.load().aps_fixture_render(_p(pool), J, _p(count), _p(pixel_offset), N, H, W,
+                                        capacity, _p(out), _stream()), "fixture_render")
+    return out
+
+
+# ------------------------------------------------------------------ scatter (a4)
+
+def scatter_samples(s, count, pixel_offset, samples, levels: int, mode: str = "hard",
+                    lam: float = 10.0, seed: int = 0, frame: int = 0):
+    _need(s, "s", _F32)
+    _need(samples, "samples", _F32)
+    N, H, W = s.shape
+    Ls = [torch.empty((N, H >> l, W >> l, 4), dtype=_F32, device=s.device) for l in range(levels)]
+    arr = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in Ls])
+    m = L.APS_HARD if mode == "hard" else L.APS_RELAXED
+    L.check(L.load().aps_scatter_samples(_p(s), _p(count), _p(pixel_offset), _p(samples),
+                                         samples.shape[0], N, H, W, levels, m, lam, seed, frame,
+                                         arr, _stream()),
+            "scatter_samples")
+    return Ls
+
+
+def assemble_features(kind: str, aux, L0=None, s=None, prev=None, mv=None, C_out: int = 16,
+                      dtype=_F32):
+    _need(aux, "aux", _F32)
+    N, H, W, _ = aux.shape
+    out = torch.empty((N, H, W, C_out), dtype=dtype, device=aux.device)
+    k = L.APS_FEAT_SAMPLER if kind == "sampler" else L.APS_FEAT_KERNEL
+    L.check(L.load().aps_assemble_features(k, _p(aux), _p(L0), _p(s), _p(prev), _p(mv), N, H, W,
+                                           C_out, _dt(dtype), _p(out), _stream()),
+            "assemble_features")
+    return out
+
+
+# ------------------------------------------------------------------ networks (a1, a5)
+
+class Net:
+    """Device weights of a conv network: fp32 OHWI masters, packed copies and the layer table.
+
+    spec: list of dicts (name, cin, cout, k, relu); weights: {name: (w[cout,k,k,cin], b[cout])}.
+    """
+
+    def __init__(self, spec, weights, dtype=_F32, device="cuda"):
+        self.spec = [dict(l) for l in spec]
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.master = {}
+        for l in self.spec:
+            w, b = weights[l["name"]]
+            self.master[l["name"]] = (torch.as_tensor(w, dtype=_F32).to(self.device).contiguous(),
+                                      torch.as_tensor(b, dtype=_F32).to(self.device).contiguous())
+        self.packed = {}
+        self.repack()
+
+    def repack(self):
+        lib = L.load()
+        desc = L.NetDesc()
+        desc.n_layers = len(self.spec)
+        desc.dtype = _dt(self.dtype)
+        for i, l in enumerate(self.spec):
+            w, b = self.master[l["name"]]
+            n = lib.aps_conv_packed_elems(l["cout"], l["k"], l["cin"])
+            pk = self.packed.get(l["name"])
+            if pk is None or pk.numel() != n:
+                pk = torch.empty(n, dtype=self.dtype, device=self.device)
+                self.packed[l["name"]] = pk
+            L.check(lib.aps_conv_pack_weights(_p(w), l["cout"], l["k"], l["cin"], desc.dtype, _p(pk),
+                                              _stream()), "pack_weights")
+            desc.layer[i] = L.ConvLayer(pk.data_ptr(), b.data_ptr(), l["cin"], l["cout"], l["k"],
+                                        int(l["relu"]))
+        self.desc = desc
+
+    def layer(self, name):
+        i = [l["name"] for l in self.spec].index(name)
+        return self.spec[i], self.packed[name], self.master[name][1]
+
+
+def conv2d(x, layer_spec, packed, bias, mode: str = "direct", x2=None, out_dtype=None,
+           ldy: int | None = None, out=None):
+    """One conv layer through aps_conv2d_fwd (mode: direct | pool2 | up2cat)."""
+    _need(x, "x")
+    N = x.shape[0]
+    if mode == "direct":
+        H, W, Cx = x.shape[1], x.shape[2], x.shape[3]
+        m, C2 = L.APS_CONV_DIRECT, 0
+    elif mode == "pool2":
+        H, W, Cx = x.shape[1] // 2, x.shape[2] // 2, x.shape[3]
+        m, C2 = L.APS_CONV_POOL2, 0
+    elif mode == "up2cat":
+        _need(x2, "x2", x.dtype)
+        H, W, Cx, C2 = x2.shape[1], x2.shape[2], x.shape[3], x2.shape[3]
+        m = L.APS_CONV_UP2_CAT
+    else:
+        raise ValueError(mode)
+    out_dtype = out_dtype or x.dtype
+    cout = layer_spec["cout"]
+    ldy = ldy or cout
+    if out is None:
+        out = torch.empty((N, H, W, ldy), dtype=out_dtype, device=x.device)
+    L.check(L.load().aps_conv2d_fwd(_p(x), _p(x2), N, H, W, Cx, C2, m, _p(packed), _p(bias), cout,
+                                    layer_spec["k"], int(layer_spec["relu"]), _dt(x.dtype), _p(out),
+                                    ldy, _dt(out_dtype), _stream()), "conv2d")
+    return out
+
+
+def density_predict(net: Net, feat, budget: float, uniform_frac: float = 1.0 / 8.0, status=None):
+    _need(feat, "feat", net.dtype)
+    N, H, W, Cf = feat.shape
+    z = torch.empty((N, H, W), dtype=_F32, device=feat.device)
+    s = torch.empty((N, H, W), dtype=_F32, device=feat.device)
+    lib = L.load()
+    width = max(l["cout"] for l in net.spec[:2])
+    nb = lib.aps_density_predict_workspace_size(N, H, W, width, _dt(net.dtype))
+    ws = WS.get(nb, feat.device)
+    L.check(lib.aps_density_predict(C.byref(net.desc), _p(feat), N, H, W, Cf, budget, uniform_frac,
+                                    _p(z), _p(s), _p(ws), nb, _p(status), _stream()),
+            "density_predict")
+    return z, s
+
+
+def round_kstride(K: int, dtype) -> int:
+    v = 8 if dtype == _BF16 else 4
+    return (K + v - 1) // v * v
+
+
+def kernel_predict(net: Net, feat, head_channels, logit_dtype=_F32):
+    _need(feat, "feat", net.dtype)
+    N, H, W, Cf = feat.shape
+    n = len(head_channels)
+    ks = [round_kstride(k, logit_dtype) for k in head_channels]
+    logits = [torch.empty((N, H >> l, W >> l, ks[l]), dtype=logit_dtype, device=feat.device)
+              for l in range(n)]
+    lib = L.load()
+    nb = lib.aps_kernel_predict_workspace_size(C.byref(net.desc), N, H, W)
+    ws = WS.get(nb, feat.device)
+    arr = (C.c_void_p * 4)(*[t.data_ptr() for t in logits])
+    karr = (C.c_int * 4)(*ks)
+    L.check(lib.aps_kernel_predict(C.byref(net.desc), _p(feat), N, H, W, Cf, n, arr,
+                                   _dt(logit_dtype), karr, _p(ws), nb, _stream()), "kernel_predict")
+    return logits
+
+
+# ------------------------------------------------------------------ reconstruction (a6-a9)
+
+def denoise_pyramid(Ls, logits, KD: int, KU: int, KT: int, prev=None, mv=None):
+    levels = len(Ls)
+    L0 = _need(Ls[0], "L0", _F32)
+    N, H, W, _ = L0.shape
+    ldt = logits[0].dtype
+    for t in logits:
+        _need(t, "logits", ldt)
+    out = torch.empty_like(L0)
+    lib = L.load()
+    nb = lib.aps_denoise_pyramid_workspace_size(N, H, W, levels)
+    ws = WS.get(nb, L0.device)
+    la = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in Ls])
+    za = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in logits])
+    ka = (C.c_int * L.APS_MAX_LEVELS)(*[t.shape[-1] for t in logits])
+    L.check(lib.aps_denoise_pyramid(la, za, _dt(ldt), ka, levels, KD, KU, KT, _p(prev), _p(mv),
+                                    N, H, W, _p(out), _p(ws), nb, _stream()), "denoise_pyramid")
+    return out
+
+
+def reproject(prev, mv, logits0, KD, KU, KT, has_upsample: bool, accum=None):
+    _need(prev, "prev", _F32)
+    N, H, W, _ = prev.shape
+    accum = torch.zeros_like(prev) if accum is None else accum
+    L.check(L.load().aps_reproject(_p(prev), _p(mv), _p(logits0), _dt(logits0.dtype),
+                                   logits0.shape[-1], KD, KU, KT, int(has_upsample), N, H, W,
+                                   _p(accum), _stream()), "reproject")
+    return accum
+
+
+def upsample(coarse, logits, KD, KU, KT, has_temporal: bool, accum=None):
+    _need(coarse, "coarse", _F32)
+    N, Hc, Wc, _ = coarse.shape
+    H, W = logits.shape[1], logits.shape[2]
+    accum = torch.zeros((N, H, W, 4), dtype=_F32, device=coarse.device) if accum is None else accum
+    L.check(L.load().aps_upsample(_p(coarse), _p(logits), _dt(logits.dtype), logits.shape[-1], KD,
+                                  KU, KT, int(has_temporal), N, H, W, _p(accum), _stream()),
+            "upsample")
+    return accum

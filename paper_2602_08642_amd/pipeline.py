@@ -1,0 +1,155 @@
+"""Per-frame path: sampler CNN -> budget normalisation -> sample mask -> (renderer) ->
+s-normalised scatter + pyramid -> kernel prediction -> gathering pyramid.
+
+Each stage is one or more libaps calls on the current stream; this module only chooses the
+configuration and passes buffers between them.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import torch
+
+from . import ops
+
+F32, BF16 = torch.float32, torch.bfloat16
+
+
+@dataclasses.dataclass(frozen=True)
+class FrameConfig:
+    name: str
+    H: int
+    W: int
+    budget: float          # samples per pixel, B
+    levels: int            # pyramid levels L
+    KD: int
+    KU: int
+    KT: int
+    temporal: bool
+    net_dtype: torch.dtype    # convolution storage / MFMA input type (fp32 accumulation)
+    logit_dtype: torch.dtype
+    widths: tuple = (32, 64, 128, 256)
+    uniform_frac: float = 1.0 / 8.0   # Sec. 3: 1/8 of the budget spread uniformly
+    kernel_net: str = "unet"          # "unet" or "cnn3" (single-level 3-layer CNN)
+
+    @property
+    def sampler_cin(self) -> int:
+        return 16 if self.temporal else 8
+
+    @property
+    def kernel_cin(self) -> int:
+        return 16
+
+    def head_channels(self):
+        out = []
+        for l in range(self.levels):
+            k = self.KD * self.KD + (self.KU * self.KU if l < self.levels - 1 else 0)
+            if l == 0 and self.temporal:
+                k += self.KT * self.KT
+            out.append(k)
+        return out
+
+
+CONFIGS = {
+    # 128x128 single frame, FP32, single-level 5x5 softmax kernel from a 3-layer CNN
+    "c1": FrameConfig("c1", 128, 128, 0.25, 1, 5, 3, 3, False, F32, F32, kernel_net="cnn3"),
+    # 1080p, 0.25 spp, FP32 throughout, U-Net kernels, 3-level pyramid 5x5, ku 3x3
+    "c2": FrameConfig("c2", 1080, 1920, 0.25, 3, 5, 3, 3, False, F32, F32),
+    # 1080p, BF16 MFMA U-Net, FP32 filtering, temporal kt 3x3
+    "c3": FrameConfig("c3", 1080, 1920, 0.25, 3, 5, 3, 3, True, BF16, BF16),
+    # training crops: 256x256, C3's reconstruction
+    "c4": FrameConfig("c4", 256, 256, 0.25, 3, 5, 3, 3, True, BF16, BF16),
+    # 4K, 0.125 spp, 4-level 7x7 pyramid, BF16 U-Net, temporal
+    "c5": FrameConfig("c5", 2160, 3840, 0.125, 4, 7, 3, 3, True, BF16, BF16),
+}
+
+
+def density_spec(cfg: FrameConfig):
+    import procgen
+    return procgen.density_cnn_spec(cfg.sampler_cin)
+
+
+def kernel_spec(cfg: FrameConfig):
+    import procgen
+    if cfg.kernel_net == "cnn3":
+        return procgen.small_kernel_cnn_spec(cfg.kernel_cin, 16, cfg.head_channels()[0])
+    return procgen.unet_spec(cfg.kernel_cin, cfg.head_channels(), cfg.widths)
+
+
+class FrameRenderer:
+    """Runs the path for one configuration with given network weights.
+
+    uniform=True is the fallback: s = B everywhere (no sampler), and, when no kernel network is
+    given, all-zero logits (box-weighted pyramid).
+    """
+
+    def __init__(self, cfg: FrameConfig, density_weights=None, kernel_weights=None,
+                 device="cuda", uniform=False):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.uniform = uniform
+        self.dnet = None
+        if not uniform:
+            self.dnet = ops.Net(density_spec(cfg), density_weights, cfg.net_dtype, self.device)
+        self.knet = None
+        if kernel_weights is not None:
+            self.knet = ops.Net(kernel_spec(cfg), kernel_weights, cfg.net_dtype, self.device)
+        self._const_logits = None
+
+    # -- stage 1: density ------------------------------------------------------------
+    def density(self, aux, prev=None, mv=None):
+        cfg = self.cfg
+        N = aux.shape[0]
+        if self.uniform:
+            return torch.full((N, cfg.H, cfg.W), cfg.budget, dtype=F32, device=self.device)
+        feat = ops.assemble_features("sampler", aux, prev=prev, mv=mv, C_out=cfg.sampler_cin,
+                                     dtype=cfg.net_dtype)
+        _, s = ops.density_predict(self.dnet, feat, cfg.budget, cfg.uniform_frac)
+        return s
+
+    # -- stage 2: sample request ---------------------------------------------------------
+    def request(self, s, seed: int, frame: int):
+        N = s.shape[0]
+        cap = int(N * self.cfg.H * self.cfg.W * (self.cfg.budget + 1.0)) + 1024
+        return ops.sample_mask(s, seed, frame, capacity=cap)
+
+    # -- stage 3: reconstruction -----------------------------------------------------------
+    def logits(self, aux, L0, s, prev=None, mv=None):
+        cfg = self.cfg
+        N = aux.shape[0]
+        if self.knet is None:
+            if self._const_logits is None or self._const_logits[0].shape[0] != N:
+                ks = cfg.head_channels()
+                self._const_logits = [
+                    torch.zeros((N, cfg.H >> l, cfg.W >> l, ops.round_kstride(ks[l], cfg.logit_dtype)),
+                                dtype=cfg.logit_dtype, device=self.device) for l in range(cfg.levels)]
+            return self._const_logits
+        feat = ops.assemble_features("kernel", aux, L0, s, prev, mv, cfg.kernel_cin, cfg.net_dtype)
+        if cfg.kernel_net == "cnn3":
+            h = feat
+            for l in self.knet.spec:
+                sp, pk, b = self.knet.layer(l["name"])
+                last = l is self.knet.spec[-1]
+                ld = ops.round_kstride(l["cout"], cfg.logit_dtype) if last else None
+                h = ops.conv2d(h, sp, pk, b, out_dtype=cfg.logit_dtype if last else None, ldy=ld)
+            return [h]
+        return ops.kernel_predict(self.knet, feat, cfg.head_channels(), cfg.logit_dtype)
+
+    def reconstruct(self, aux, s, req, samples, seed: int, frame: int, prev=None, mv=None,
+                    mode="hard", lam=10.0):
+        cfg = self.cfg
+        Ls = ops.scatter_samples(s, req["count"], req["pixel_offset"], samples, cfg.levels, mode,
+                                 lam, seed, frame)
+        use_prev = prev if cfg.temporal else None
+        use_mv = mv if cfg.temporal else None
+        z = self.logits(aux, Ls[0], s, use_prev, use_mv)
+        out = ops.denoise_pyramid(Ls, z, cfg.KD, cfg.KU, cfg.KT, use_prev, use_mv)
+        return out, Ls, z
+
+    def step(self, aux, render, seed: int, frame: int, prev=None, mv=None):
+        """One frame; render(req) -> samples [capacity, 4] stands in for the path tracer."""
+        s = self.density(aux, prev if self.cfg.temporal else None, mv if self.cfg.temporal else None)
+        req = self.request(s, seed, frame)
+        samples = render(req)
+        out, Ls, z = self.reconstruct(aux, s, req, samples, seed, frame, prev, mv)
+        return dict(out=out, s=s, req=req, L=Ls, logits=z)
