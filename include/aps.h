@@ -198,6 +198,117 @@ int aps_upsample(const float* coarse, const void* logits, int logit_dtype, int k
                  int KU, int KT, int has_temporal, int N, int H, int W, float* accum_out,
                  void* stream);
 
+/* ---------------------------------------------------------------- a10: backward passes
+ * All gradients are float32 unless a dtype argument says otherwise.  "Written" outputs are
+ * overwritten; "accumulated" ones are added to (the caller zeroes them first). */
+
+/* Gathering pyramid (App. A) backward.  The coarse reconstructed levels are recomputed from
+ * L and the logits (not stored), then levels run fine to coarse:
+ *   grad_logits[l] [N,H_l,W_l,gstride[l]] (grad_dtype F32|BF16; written, padding zeroed):
+ *     w_k (<g, v_k> - <g, y>) for the joint softmax (eqs. app-softmax-mid/full);
+ *   grad_L[l] [N,H_l,W_l,4] (written): the transpose of the kd gather (eq. app-gather),
+ *     a gather over each input pixel's edge-clamped preimages (deterministic);
+ *   grad_prev [N,H,W,4] (accumulated, nullable): the transpose of the kt gather and of the
+ *     bilinear warp (eq. app-recon-full), by float atomics (order not fixed).
+ * Arguments otherwise as aps_denoise_pyramid. */
+size_t aps_denoise_pyramid_bwd_workspace_size(int N, int H, int W, int levels, int KD, int KU,
+                                              int KT, int temporal);
+int aps_denoise_pyramid_bwd(const float* const* L, const void* const* logits, int logit_dtype,
+                            const int* kstride, int levels, int KD, int KU, int KT,
+                            const float* prev, const float* mv, int N, int H, int W,
+                            const float* grad_out, void* const* grad_logits, int grad_dtype,
+                            const int* gstride, float* const* grad_L, float* grad_prev, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Scatter backward (Sec. 4.2 eq. stoch_rnoisy, Sec. 4.3 eq. relaxed_holdout): grad_s (written,
+ * or accumulated when accumulate != 0) = <dLoss/dL0, dL0/ds> with
+ *   dL0/ds = -L0/s + (S_holdout/s) dw/dp,  dw/dp = h lambda u / p^2 inside the relaxed ramp,
+ *   0 on its clamped parts and in hard mode;
+ * dLoss/dL0 collects grad_L[l] / 4^l of every pyramid ancestor (eq. app-pyramid).
+ * Arguments as aps_scatter_samples; grad_L[l] float32 RGBA [N, H>>l, W>>l]. */
+int aps_scatter_samples_bwd(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                            const float* samples, int64_t n_samples, int N, int H, int W,
+                            int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
+                            const float* const* grad_L, float* grad_s, int accumulate,
+                            void* stream);
+
+/* Budget normalisation backward (Sec. 3): grad_z (written) = c1 sm (g - sum(sm g)) per frame,
+ * c1 = (1-f) B Npx; fixed-tree reductions (deterministic). */
+size_t aps_normalize_bwd_workspace_size(int N, int H, int W);
+int aps_normalize_density_bwd(const float* z, int N, int H, int W, float budget_spp,
+                              float uniform_frac, const float* grad_s, float* grad_z, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Feature assembly backward: accumulates into grad_L0 (RGB of float32 RGBA [N,H,W,4]),
+ * grad_s [N,H,W], and, through the warp, grad_prev [N,H,W,4] (float atomics); each output is
+ * skipped when NULL.  grad_feat [N,H,W,C] in feat_dtype. */
+int aps_assemble_features_bwd(int kind, const float* L0, const float* prev, const float* mv,
+                              int N, int H, int W, int C, int feat_dtype, const void* grad_feat,
+                              float* grad_L0, float* grad_s, float* grad_prev, void* stream);
+
+/* Data-gradient operator of a conv layer: the same MFMA kernel with w'[ci][tap][co] =
+ * w[co][k*k-1-tap][ci].  packed holds aps_conv_packed_elems(Cin, ksize, Cout) elements. */
+int aps_conv_pack_weights_dgrad(const float* w, int Cout, int ksize, int Cin, int dtype,
+                                void* packed, void* stream);
+
+/* dX [N,H,W,Cin] (written, dtype) = gradient w.r.t. the conv's transformed input, from
+ * dy [N,H,W,ldy] (channels >= Cout ignored) masked by ymask > 0 when ymask (the layer's
+ * post-ReLU output [N,H,W,Cout], then ldy == Cout) is given.  ldy*sizeof(dtype) % 16 == 0. */
+int aps_conv2d_bwd_data(const void* dy, const void* ymask, int ldy, int N, int H, int W, int Cout,
+                        const void* packed_wT, int ksize, int Cin, int dtype, void* dX,
+                        void* stream);
+
+/* Transpose of the fused input transform (H, W = the conv's output size):
+ *   APS_CONV_DIRECT : dx [N,H,W,Cx] (+)= dX
+ *   APS_CONV_POOL2  : dx [N,2H,2W,Cx] (+)= dX / 4 on each 2x2 child
+ *   APS_CONV_UP2_CAT: dx [N,H/2,W/2,Cx] (+)= sum of dX[..., :Cx] over the 2x2 children;
+ *                     dx2 [N,H,W,C2] (+)= dX[..., Cx:]
+ * "(+)=" adds when the matching accumulate flag is set, else writes. */
+int aps_conv_input_grad(int mode, const void* dX, int N, int H, int W, int Cx, int C2, int dtype,
+                        void* dx, int accumulate, void* dx2, int accumulate2, void* stream);
+
+/* Weight and bias gradients of a conv layer (MFMA, split over pixel blocks, fixed-order
+ * reduction: deterministic): dw [Cout][k][k][Cin] float32 (written) = sum over pixels of
+ * dy (masked as above) times the transformed input; db [Cout] float32 (written, nullable).
+ * Input arguments as aps_conv2d_fwd; Cout <= 256. */
+size_t aps_conv2d_bwd_weight_workspace_size(int N, int H, int W, int Cx, int C2, int Cout,
+                                            int ksize);
+int aps_conv2d_bwd_weight(const void* x, const void* x2, int mode, int N, int H, int W, int Cx,
+                          int C2, const void* dy, const void* ymask, int ldy, int Cout, int ksize,
+                          int dtype, float* dw, float* db, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* ---------------------------------------------------------------- a11: training
+ * Loss of Sec. 6.3 (eqs. loss_spatial, loss_temporal, loss_combined, visual mask m = 1) on the
+ * tonemapped images of Sec. 5: I = sRGB(tau(alpha (sat_beta(log(max(L,0) + 1e-4)) + k); s, h)),
+ * params [N][5] = (k, alpha, beta, s, h) per frame (device).  loss (device scalar, written) =
+ * mean over pixels and RGB of max(1.25 |dI - dI_ref|, |I - I_ref|), with dI = I - W(I_prev) and
+ * the temporal term 0 where the back-projection leaves the frame (or without prev_out).
+ * grad_out [N,H,W,4] written; grad_prev [N,H,W,4] accumulated through the warp (nullable). */
+size_t aps_tmo_loss_workspace_size(int N, int H, int W);
+int aps_tmo_loss(const float* out, const float* ref, const float* prev_out, const float* prev_ref,
+                 const float* mv, const float* params, int N, int H, int W, float* loss,
+                 float* grad_out, float* grad_prev, void* ws, size_t ws_bytes, void* stream);
+
+/* AdamW with decoupled weight decay on float32 master parameters (Sec. 6.3 uses
+ * beta = (0.8, 0.985), weight decay 0.02); step >= 1 is the 1-based step count for the bias
+ * corrections; the gradient is multiplied by grad_scale first. */
+int aps_adamw_step(float* param, float* m, float* v, const float* grad, int64_t n, float lr,
+                   float beta1, float beta2, float eps, float weight_decay, int step,
+                   float grad_scale, void* stream);
+
+/* Layout / dtype copy: dst[p][c] = src[p][c] for c < C, 0 for C <= c < dst_ld, p < npix
+ * (F32 or BF16 on either side; bf16 by round to nearest even). */
+int aps_copy_channels(const void* src, int src_dtype, int src_ld, void* dst, int dst_dtype,
+                      int dst_ld, int64_t npix, int C, void* stream);
+
+/* x[i] *= *scale (scale a device scalar), i < n. */
+int aps_scale_by(float* x, int64_t n, const float* scale, void* stream);
+
+/* out (device scalar) = sum of x^2, fixed-order reduction (gradient-norm guard). */
+size_t aps_sumsq_workspace_size(int64_t n);
+int aps_sumsq(const float* x, int64_t n, float* out, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,27 @@ SIGNATURES = {
     "aps_denoise_pyramid": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, P, P, SZ, P]),
     "aps_reproject": (I, [P, P, P, I, I, I, I, I, I, I, I, I, P, P]),
     "aps_upsample": (I, [P, P, I, I, I, I, I, I, I, I, I, P, P]),
+    # backward
+    "aps_denoise_pyramid_bwd_workspace_size": (SZ, [I, I, I, I, I, I, I, I]),
+    "aps_denoise_pyramid_bwd": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, P, P, I, P, P, P, P,
+                                    SZ, P]),
+    "aps_scatter_samples_bwd": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P, I, P]),
+    "aps_normalize_bwd_workspace_size": (SZ, [I, I, I]),
+    "aps_normalize_density_bwd": (I, [P, I, I, I, F, F, P, P, P, SZ, P]),
+    "aps_assemble_features_bwd": (I, [I, P, P, P, I, I, I, I, I, P, P, P, P, P]),
+    "aps_conv_pack_weights_dgrad": (I, [P, I, I, I, I, P, P]),
+    "aps_conv2d_bwd_data": (I, [P, P, I, I, I, I, I, P, I, I, I, P, P]),
+    "aps_conv_input_grad": (I, [I, P, I, I, I, I, I, I, P, I, P, I, P]),
+    "aps_conv2d_bwd_weight_workspace_size": (SZ, [I, I, I, I, I, I, I]),
+    "aps_conv2d_bwd_weight": (I, [P, P, I, I, I, I, I, I, P, P, I, I, I, I, P, P, P, SZ, P]),
+    # training
+    "aps_tmo_loss_workspace_size": (SZ, [I, I, I]),
+    "aps_tmo_loss": (I, [P, P, P, P, P, P, I, I, I, P, P, P, P, SZ, P]),
+    "aps_adamw_step": (I, [P, P, P, P, I64, F, F, F, F, F, I, F, P]),
+    "aps_copy_channels": (I, [P, I, I, P, I, I, I64, I, P]),
+    "aps_scale_by": (I, [P, I64, P, P]),
+    "aps_sumsq_workspace_size": (SZ, [I64]),
+    "aps_sumsq": (I, [P, I64, P, P, SZ, P]),
 }
 
 _lib = None

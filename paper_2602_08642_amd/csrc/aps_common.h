@@ -39,6 +39,12 @@ __device__ __host__ inline uint16_t f2bf(float f) {
 __device__ __host__ inline float bf2f(uint16_t h) {
   return __builtin_bit_cast(float, ((uint32_t)h) << 16);
 }
+template <typename T>
+__device__ inline T f2t(float v);
+template <>
+__device__ inline float f2t<float>(float v) { return v; }
+template <>
+__device__ inline uint16_t f2t<uint16_t>(float v) { return f2bf(v); }
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) --------------------------------------------
 __device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {

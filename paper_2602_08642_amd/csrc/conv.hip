@@ -15,6 +15,7 @@ namespace {
 
 constexpr int kChunk = 32;
 constexpr int kMaxTM = 4;
+constexpr int kModeReluMask = 3;  // internal staging mode of the data-gradient convolution
 
 struct ConvArgs {
   const void* x;
@@ -78,8 +79,25 @@ __device__ inline void stage8(const ConvArgs& a, int n, int iy, int ix, int ci, 
     return;
   }
   const T* x = static_cast<const T*>(a.x);
-  if (a.mode == APS_CONV_DIRECT) {
+  if ((a.mode == APS_CONV_DIRECT || a.mode == kModeReluMask) && ci + 8 > a.Cx) {
+    // channel tail of a row whose stride is not a multiple of 8 (padded logit gradients)
+    const size_t o = (((size_t)n * a.H + iy) * a.W + ix) * a.Cx + ci;
+    const T* y = static_cast<const T*>(a.x2);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const bool ok = ci + e < a.Cx && (a.mode == APS_CONV_DIRECT || Ld<T>::get(y, o + e) > 0.f);
+      dst[e] = ok ? x[o + e] : T(0);
+    }
+  } else if (a.mode == APS_CONV_DIRECT) {
     copy8(dst, x + (((size_t)n * a.H + iy) * a.W + ix) * a.Cx + ci);
+  } else if (a.mode == kModeReluMask) {
+    // x = dLoss/dy, x2 = y (post-ReLU output, same layout): stage dy where y > 0, else 0
+    const size_t o = (((size_t)n * a.H + iy) * a.W + ix) * a.Cx + ci;
+    const V8f g = load8(x + o), y = load8(static_cast<const T*>(a.x2) + o);
+    V8f r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r.v[e] = y.v[e] > 0.f ? g.v[e] : 0.f;
+    store8(dst, r);
   } else if (a.mode == APS_CONV_POOL2) {
     const int W2 = 2 * a.W;
     const T* p = x + (((size_t)n * 2 * a.H + 2 * iy) * W2 + 2 * ix) * a.Cx + ci;
@@ -214,7 +232,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
       float v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        float t = acc[m][j][q] + (co0 + q < a.Cout ? a.bias[co0 + q] : 0.f);
+        float t = acc[m][j][q] + (co0 + q < a.Cout && a.bias ? a.bias[co0 + q] : 0.f);
         v[q] = a.relu ? fmaxf(t, 0.f) : t;
       }
       store_out<TO>(py, a.ldy, co0, a.Cout, v);
@@ -225,9 +243,11 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 // ---- weight packing: OHWI fp32 -> fragment order --------------------------------------
 // packed[(((ct * KS*KS + tap) * nchunk + c) * 64 + lane) * 8 + e] =
 //     w[co = 16 ct + lane % 16][tap][ci = 32 c + 8 (lane / 16) + e]   (0 outside)
+// transpose = 1 packs the data-gradient operator of w: a conv with Cout' = Cin, Cin' = Cout and
+//     w'[co'][tap][ci'] = w[ci'][KS*KS - 1 - tap][co']   (channels swapped, taps flipped).
 template <typename T>
 __global__ void k_pack(const float* __restrict__ w, int Cout, int KS, int Cin, int nchunk,
-                       size_t total, T* __restrict__ out) {
+                       size_t total, T* __restrict__ out, int transpose) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= total) return;
   const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
@@ -238,7 +258,9 @@ __global__ void k_pack(const float* __restrict__ w, int Cout, int KS, int Cin, i
   const int ct = (int)(r / (KS * KS));
   const int co = ct * 16 + (lane & 15), ci = c * kChunk + (lane >> 4) * 8 + e;
   float v = 0.f;
-  if (co < Cout && ci < Cin) v = w[((size_t)co * KS * KS + tap) * Cin + ci];
+  if (co < Cout && ci < Cin)
+    v = transpose ? w[((size_t)ci * KS * KS + (KS * KS - 1 - tap)) * Cout + co]
+                  : w[((size_t)co * KS * KS + tap) * Cin + ci];
   if constexpr (sizeof(T) == 2) out[i] = f2bf(v);
   else out[i] = v;
 }
@@ -278,6 +300,236 @@ void dispatch_ks(const ConvArgs& a, int KS, hipStream_t st) {
   else dispatch_tiles<T, TO, 1>(a, st);
 }
 
+// ======================================================================== backward
+// ---- data gradient: transposes of the fused input transforms ----------------------------
+// POOL2:    dx[n][2y+a][2x+b][c] (+)= dX[n][y][x][c] / 4
+// UP2_CAT:  dx[n][Y][X][c] (+)= sum_{a,b} dX[n][2Y+a][2X+b][c] (c < Cx);
+//           dx2[n][y][x][c] (+)= dX[n][y][x][Cx + c]
+// DIRECT:   dx (+)= dX
+template <typename T>
+__global__ __launch_bounds__(256) void k_input_grad(int mode, const T* __restrict__ dX, int N,
+                                                    int H, int W, int Cx, int C2,
+                                                    T* __restrict__ dx, int acc, T* __restrict__ dx2,
+                                                    int acc2) {
+  const int Cin = Cx + C2;
+  size_t total;
+  if (mode == APS_CONV_POOL2) total = (size_t)N * 2 * H * 2 * W * Cx;
+  else if (mode == APS_CONV_UP2_CAT) total = (size_t)N * (H / 2) * (W / 2) * Cx + (size_t)N * H * W * C2;
+  else total = (size_t)N * H * W * Cx;
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  if (mode == APS_CONV_POOL2) {
+    const int c = (int)(i % Cx);
+    const size_t pf = i / Cx;
+    const int xf = (int)(pf % (2 * W)), yf = (int)((pf / (2 * W)) % (2 * H)), n = (int)(pf / ((size_t)4 * H * W));
+    const float v = 0.25f * Ld<T>::get(dX, (((size_t)n * H + yf / 2) * W + xf / 2) * Cin + c);
+    dx[i] = f2t<T>(acc ? Ld<T>::get(dx, i) + v : v);
+  } else if (mode == APS_CONV_UP2_CAT) {
+    const size_t n1 = (size_t)N * (H / 2) * (W / 2) * Cx;
+    if (i < n1) {
+      const int c = (int)(i % Cx);
+      const size_t pc = i / Cx;
+      const int Wh = W / 2, Hh = H / 2;
+      const int X = (int)(pc % Wh), Y = (int)((pc / Wh) % Hh), n = (int)(pc / ((size_t)Wh * Hh));
+      float v = 0.f;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          v += Ld<T>::get(dX, (((size_t)n * H + 2 * Y + a) * W + 2 * X + b) * Cin + c);
+      dx[i] = f2t<T>(acc ? Ld<T>::get(dx, i) + v : v);
+    } else {
+      const size_t k = i - n1;
+      const int c = (int)(k % C2);
+      const size_t p = k / C2;
+      const float v = Ld<T>::get(dX, p * Cin + Cx + c);
+      dx2[k] = f2t<T>(acc2 ? Ld<T>::get(dx2, k) + v : v);
+    }
+  } else {
+    const float v = Ld<T>::get(dX, i);
+    dx[i] = f2t<T>(acc ? Ld<T>::get(dx, i) + v : v);
+  }
+}
+
+// ---- weight gradient: dW[co][tap][ci] = sum_px dY[px][co] * X[px + d_tap][ci] -------------
+// M = cout (16 per MFMA tile), N = cin (16), K = pixels: 2-row x 64-column pixel blocks, the
+// block's dY (cout-major) and its input tile with halo (cin-major) staged in LDS.  Pixel blocks
+// are split across workgroups; each split writes its partial dW and a second pass sums the
+// splits in a fixed order (deterministic).
+constexpr int kWgRows = 2, kWgCols = 64;
+
+struct WgradArgs {
+  ConvArgs in;          // the forward input (x, x2, N, H, W, Cx, C2, mode)
+  const void* dy;       // [N, H, W, ldy]
+  const void* ymask;    // post-ReLU output [N, H, W, Cout] or null
+  int ldy, Cout, nchunk;
+  int nrb, ncb, nblocks, bps;
+  int CoutP, CinP;
+  float* part;          // [splits][CoutP][KS*KS][CinP]
+};
+
+template <typename T>
+__device__ inline void frag_load_lds(Frag<T>& f, const T* p);
+template <>
+__device__ inline void frag_load_lds<float>(Frag<float>& f, const float* p) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) f.v[e] = p[e];
+}
+template <>
+__device__ inline void frag_load_lds<uint16_t>(Frag<uint16_t>& f, const uint16_t* p) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) f.v[e] = p[e];
+}
+
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+  constexpr int R = KS / 2;
+  constexpr int NP = kWgRows * kWgCols;
+  constexpr int XW = kWgCols + 2 * R, XH = kWgRows + 2 * R;
+  constexpr int YS = NP + 8;        // per-cout row of dY (elements)
+  constexpr int XS = XH * XW + 8;   // per-cin plane of X (elements)
+  __shared__ __attribute__((aligned(16))) T dYs[32 * YS];
+  __shared__ __attribute__((aligned(16))) T Xs[32 * XS];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int split = blockIdx.x, cot = blockIdx.y, c = blockIdx.z;
+  const int m = wave & 1, j = wave >> 1;
+  const int H = a.in.H, W = a.in.W;
+  const T* dy = static_cast<const T*>(a.dy);
+  const T* ym = static_cast<const T*>(a.ymask);
+
+  f32x4 acc[KS * KS];
+#pragma unroll
+  for (int t = 0; t < KS * KS; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int b1 = min(a.nblocks, (split + 1) * a.bps);
+  for (int blk = split * a.bps; blk < b1; ++blk) {
+    const int n = blk / (a.nrb * a.ncb), rb = (blk / a.ncb) % a.nrb, cb = blk % a.ncb;
+    const int y0 = rb * kWgRows, x0 = cb * kWgCols;
+    for (int it = tid; it < NP * 4; it += 256) {
+      const int g = it & 3, p = it >> 2;
+      const int py = y0 + p / kWgCols, px = x0 + p % kWgCols;
+      const int co = cot * 32 + g * 8;
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = 0.f;
+      if (py < H && px < W) {
+        const size_t pix = ((size_t)n * H + py) * W + px;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (co + e < a.Cout) {
+            float g_ = Ld<T>::get(dy, pix * a.ldy + co + e);
+            if (ym && !(Ld<T>::get(ym, pix * a.Cout + co + e) > 0.f)) g_ = 0.f;
+            v[e] = g_;
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dYs[(g * 8 + e) * YS + p] = f2t<T>(v[e]);
+    }
+    for (int it = tid; it < XH * XW * 4; it += 256) {
+      const int g = it & 3, p = it >> 2;
+      const int r = p / XW, col = p % XW;
+      T tmp[8];
+      stage8<T>(a.in, n, y0 - R + r, x0 - R + col, c * kChunk + g * 8, tmp);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Xs[(g * 8 + e) * XS + p] = tmp[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kWgRows; ++r) {
+#pragma unroll
+      for (int s = 0; s < kWgCols / 32; ++s) {
+        Frag<T> af;
+        frag_load_lds(af, dYs + (m * 16 + (lane & 15)) * YS + r * kWgCols + 32 * s + 8 * (lane >> 4));
+#pragma unroll
+        for (int tap = 0; tap < KS * KS; ++tap) {
+          const int dyy = tap / KS - R, dxx = tap % KS - R;
+          Frag<T> bf;
+          frag_load_lds(bf, Xs + (j * 16 + (lane & 15)) * XS + (r + R + dyy) * XW +
+                                (32 * s + 8 * (lane >> 4) + R + dxx));
+          acc[tap] = mma(af, bf, acc[tap]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int ci = c * kChunk + j * 16 + (lane & 15);
+#pragma unroll
+  for (int tap = 0; tap < KS * KS; ++tap)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int co = cot * 32 + m * 16 + 4 * (lane >> 4) + q;
+      a.part[(((size_t)split * a.CoutP + co) * KS * KS + tap) * a.CinP + ci] = acc[tap][q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int splits,
+                                                      int Cout, int KK, int Cin, int CoutP,
+                                                      int CinP, float* __restrict__ dw) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)Cout * KK * Cin) return;
+  const int ci = (int)(i % Cin);
+  const int tap = (int)((i / Cin) % KK);
+  const int co = (int)(i / ((size_t)Cin * KK));
+  float s = 0.f;
+  for (int k = 0; k < splits; ++k) s += part[(((size_t)k * CoutP + co) * KK + tap) * CinP + ci];
+  dw[i] = s;
+}
+
+// db[co] = sum_px dY[px][co] (masked): per-block partials, then a fixed-order sum
+template <typename T>
+__global__ __launch_bounds__(256) void k_bias_partial(const T* __restrict__ dy,
+                                                      const T* __restrict__ ym, int ldy, int Cout,
+                                                      size_t npix, size_t per,
+                                                      float* __restrict__ part) {
+  const int co = threadIdx.x;
+  if (co >= Cout) return;
+  const size_t p0 = (size_t)blockIdx.x * per, p1 = min(npix, p0 + per);
+  float s = 0.f;
+  for (size_t p = p0; p < p1; ++p) {
+    float g = Ld<T>::get(dy, p * ldy + co);
+    if (ym && !(Ld<T>::get(ym, p * Cout + co) > 0.f)) g = 0.f;
+    s += g;
+  }
+  part[(size_t)blockIdx.x * Cout + co] = s;
+}
+
+__global__ __launch_bounds__(256) void k_bias_reduce(const float* __restrict__ part, int nb,
+                                                     int Cout, float* __restrict__ db) {
+  const int co = blockIdx.x * 256 + threadIdx.x;
+  if (co >= Cout) return;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) s += part[(size_t)b * Cout + co];
+  db[co] = s;
+}
+
+struct WgradPlan {
+  int nrb, ncb, nblocks, splits, bps, CoutP, CinP, nchunk;
+  size_t part_bytes, bias_blocks, bias_per;
+};
+
+WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int KS) {
+  WgradPlan p{};
+  p.nrb = (H + kWgRows - 1) / kWgRows;
+  p.ncb = (W + kWgCols - 1) / kWgCols;
+  p.nblocks = N * p.nrb * p.ncb;
+  p.nchunk = (Cin + kChunk - 1) / kChunk;
+  p.CoutP = (Cout + 31) / 32 * 32;
+  p.CinP = p.nchunk * kChunk;
+  const int tiles = (p.CoutP / 32) * p.nchunk;
+  int want = (1024 + tiles - 1) / tiles;
+  if (want > 256) want = 256;
+  if (want < 1) want = 1;
+  if (want > p.nblocks) want = p.nblocks;
+  p.bps = (p.nblocks + want - 1) / want;
+  p.splits = (p.nblocks + p.bps - 1) / p.bps;
+  p.part_bytes = (size_t)p.splits * p.CoutP * KS * KS * p.CinP * sizeof(float);
+  const size_t npix = (size_t)N * H * W;
+  p.bias_per = 1024;
+  p.bias_blocks = (npix + p.bias_per - 1) / p.bias_per;
+  return p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -287,24 +539,37 @@ size_t aps_conv_packed_elems(int Cout, int ksize, int Cin) {
   return packed_elems(Cout, ksize, Cin);
 }
 
-int aps_conv_pack_weights(const float* w, int Cout, int ksize, int Cin, int dtype, void* packed,
-                          void* stream) {
+static int pack_impl(const float* w, int Cout, int ksize, int Cin, int dtype, void* packed,
+                     void* stream, int transpose) {
   if (!w || !packed) return APS_ERR_NULL;
   if (Cout <= 0 || Cin <= 0) return APS_ERR_SHAPE;
   if (ksize != 1 && ksize != 3) return APS_ERR_UNSUPPORTED;
-  const size_t total = packed_elems(Cout, ksize, Cin);
-  const int nchunk = (Cin + kChunk - 1) / kChunk;
+  // the packed operator's sizes
+  const int co = transpose ? Cin : Cout, ci = transpose ? Cout : Cin;
+  const size_t total = packed_elems(co, ksize, ci);
+  const int nchunk = (ci + kChunk - 1) / kChunk;
   const int blocks = (int)((total + 255) / 256);
   hipStream_t st = as_stream(stream);
   if (dtype == APS_F32)
-    k_pack<float><<<blocks, 256, 0, st>>>(w, Cout, ksize, Cin, nchunk, total, static_cast<float*>(packed));
+    k_pack<float><<<blocks, 256, 0, st>>>(w, co, ksize, ci, nchunk, total,
+                                          static_cast<float*>(packed), transpose);
   else if (dtype == APS_BF16)
-    k_pack<uint16_t><<<blocks, 256, 0, st>>>(w, Cout, ksize, Cin, nchunk, total,
-                                             static_cast<uint16_t*>(packed));
+    k_pack<uint16_t><<<blocks, 256, 0, st>>>(w, co, ksize, ci, nchunk, total,
+                                             static_cast<uint16_t*>(packed), transpose);
   else
     return APS_ERR_UNSUPPORTED;
   APS_LAUNCH_CHECK();
   return APS_OK;
+}
+
+int aps_conv_pack_weights(const float* w, int Cout, int ksize, int Cin, int dtype, void* packed,
+                          void* stream) {
+  return pack_impl(w, Cout, ksize, Cin, dtype, packed, stream, 0);
+}
+
+int aps_conv_pack_weights_dgrad(const float* w, int Cout, int ksize, int Cin, int dtype,
+                                void* packed, void* stream) {
+  return pack_impl(w, Cout, ksize, Cin, dtype, packed, stream, 1);
 }
 
 int aps_conv2d_fwd(const void* x, const void* x2, int N, int H, int W, int Cx, int C2, int mode,
@@ -346,6 +611,162 @@ int aps_conv2d_fwd(const void* x, const void* x2, int N, int H, int W, int Cx, i
   else if (dtype == APS_BF16 && y_dtype == APS_BF16) dispatch_ks<uint16_t, uint16_t>(a, ksize, st);
   else if (dtype == APS_BF16 && y_dtype == APS_F32) dispatch_ks<uint16_t, float>(a, ksize, st);
   else return APS_ERR_UNSUPPORTED;
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================== backward C ABI
+extern "C" {
+
+int aps_conv2d_bwd_data(const void* dy, const void* ymask, int ldy, int N, int H, int W, int Cout,
+                        const void* packed_wT, int ksize, int Cin, int dtype, void* dX,
+                        void* stream) {
+  if (N < 0 || H < 0 || W < 0 || Cout <= 0 || Cin <= 0 || ldy < Cout) return APS_ERR_SHAPE;
+  if (ksize != 1 && ksize != 3) return APS_ERR_UNSUPPORTED;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!dy || !packed_wT || !dX) return APS_ERR_NULL;
+  const size_t es = dtype == APS_BF16 ? 2 : 4;
+  if ((ldy * es) % 16) return APS_ERR_SHAPE;
+  if (ymask && ldy != Cout) return APS_ERR_SHAPE;
+  ConvArgs a{};
+  a.x = dy;
+  a.x2 = ymask;
+  a.N = N;
+  a.H = H;
+  a.W = W;
+  a.Cx = ldy;
+  a.C2 = 0;
+  a.mode = ymask ? kModeReluMask : APS_CONV_DIRECT;
+  a.wp = packed_wT;
+  a.bias = nullptr;
+  a.Cout = Cin;
+  a.nchunk = (ldy + kChunk - 1) / kChunk;
+  if (a.nchunk != (Cout + kChunk - 1) / kChunk) return APS_ERR_SHAPE;
+  a.y = dX;
+  a.ldy = Cin;
+  a.relu = 0;
+  hipStream_t st = as_stream(stream);
+  if (dtype == APS_F32) dispatch_ks<float, float>(a, ksize, st);
+  else if (dtype == APS_BF16) dispatch_ks<uint16_t, uint16_t>(a, ksize, st);
+  else return APS_ERR_UNSUPPORTED;
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+int aps_conv_input_grad(int mode, const void* dX, int N, int H, int W, int Cx, int C2, int dtype,
+                        void* dx, int accumulate, void* dx2, int accumulate2, void* stream) {
+  if (N < 0 || H < 0 || W < 0 || Cx <= 0 || C2 < 0) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!dX || !dx) return APS_ERR_NULL;
+  size_t total;
+  if (mode == APS_CONV_POOL2) {
+    if (C2) return APS_ERR_SHAPE;
+    total = (size_t)N * 4 * H * W * Cx;
+  } else if (mode == APS_CONV_UP2_CAT) {
+    if (!dx2 || C2 <= 0) return APS_ERR_NULL;
+    if (H % 2 || W % 2) return APS_ERR_SHAPE;
+    total = (size_t)N * (H / 2) * (W / 2) * Cx + (size_t)N * H * W * C2;
+  } else if (mode == APS_CONV_DIRECT) {
+    if (C2) return APS_ERR_SHAPE;
+    total = (size_t)N * H * W * Cx;
+  } else {
+    return APS_ERR_ARG;
+  }
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  hipStream_t st = as_stream(stream);
+  if (dtype == APS_F32)
+    k_input_grad<float><<<blocks, 256, 0, st>>>(mode, static_cast<const float*>(dX), N, H, W, Cx, C2,
+                                                static_cast<float*>(dx), accumulate,
+                                                static_cast<float*>(dx2), accumulate2);
+  else if (dtype == APS_BF16)
+    k_input_grad<uint16_t><<<blocks, 256, 0, st>>>(mode, static_cast<const uint16_t*>(dX), N, H, W,
+                                                   Cx, C2, static_cast<uint16_t*>(dx), accumulate,
+                                                   static_cast<uint16_t*>(dx2), accumulate2);
+  else
+    return APS_ERR_UNSUPPORTED;
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+size_t aps_conv2d_bwd_weight_workspace_size(int N, int H, int W, int Cx, int C2, int Cout,
+                                            int ksize) {
+  if (N <= 0 || H <= 0 || W <= 0 || Cout <= 0 || Cx <= 0) return 256;
+  const WgradPlan p = wgrad_plan(N, H, W, Cx + C2, Cout, ksize);
+  return ((p.part_bytes + 255) / 256) * 256 + p.bias_blocks * Cout * sizeof(float) + 256;
+}
+
+int aps_conv2d_bwd_weight(const void* x, const void* x2, int mode, int N, int H, int W, int Cx,
+                          int C2, const void* dy, const void* ymask, int ldy, int Cout, int ksize,
+                          int dtype, float* dw, float* db, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (N < 0 || H < 0 || W < 0 || Cx <= 0 || C2 < 0 || Cout <= 0 || ldy < Cout) return APS_ERR_SHAPE;
+  if (ksize != 1 && ksize != 3) return APS_ERR_UNSUPPORTED;
+  if (Cx % 8 || C2 % 8 || Cout > 256) return APS_ERR_UNSUPPORTED;
+  if (mode == APS_CONV_UP2_CAT) {
+    if (!x2 || C2 <= 0) return APS_ERR_NULL;
+    if (H % 2 || W % 2) return APS_ERR_SHAPE;
+  } else if (mode == APS_CONV_DIRECT || mode == APS_CONV_POOL2) {
+    if (C2) return APS_ERR_SHAPE;
+  } else {
+    return APS_ERR_ARG;
+  }
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!x || !dy || !dw) return APS_ERR_NULL;
+  if (!ws || ws_bytes < aps_conv2d_bwd_weight_workspace_size(N, H, W, Cx, C2, Cout, ksize))
+    return APS_ERR_WORKSPACE;
+  const int Cin = Cx + C2;
+  const WgradPlan p = wgrad_plan(N, H, W, Cin, Cout, ksize);
+  WgradArgs a{};
+  a.in.x = x;
+  a.in.x2 = x2;
+  a.in.N = N;
+  a.in.H = H;
+  a.in.W = W;
+  a.in.Cx = Cx;
+  a.in.C2 = C2;
+  a.in.mode = mode;
+  a.dy = dy;
+  a.ymask = ymask;
+  a.ldy = ldy;
+  a.Cout = Cout;
+  a.nchunk = p.nchunk;
+  a.nrb = p.nrb;
+  a.ncb = p.ncb;
+  a.nblocks = p.nblocks;
+  a.bps = p.bps;
+  a.CoutP = p.CoutP;
+  a.CinP = p.CinP;
+  a.part = static_cast<float*>(ws);
+  float* bpart = reinterpret_cast<float*>(static_cast<char*>(ws) + ((p.part_bytes + 255) / 256) * 256);
+  hipStream_t st = as_stream(stream);
+  dim3 grid(p.splits, p.CoutP / 32, p.nchunk);
+  if (dtype == APS_F32) {
+    if (ksize == 3) k_wgrad<float, 3><<<grid, 256, 0, st>>>(a);
+    else k_wgrad<float, 1><<<grid, 256, 0, st>>>(a);
+  } else if (dtype == APS_BF16) {
+    if (ksize == 3) k_wgrad<uint16_t, 3><<<grid, 256, 0, st>>>(a);
+    else k_wgrad<uint16_t, 1><<<grid, 256, 0, st>>>(a);
+  } else {
+    return APS_ERR_UNSUPPORTED;
+  }
+  const size_t nw = (size_t)Cout * ksize * ksize * Cin;
+  k_wgrad_reduce<<<(unsigned)((nw + 255) / 256), 256, 0, st>>>(a.part, p.splits, Cout,
+                                                                ksize * ksize, Cin, p.CoutP, p.CinP,
+                                                                dw);
+  if (db) {
+    const size_t npix = (size_t)N * H * W;
+    if (dtype == APS_F32)
+      k_bias_partial<float><<<(unsigned)p.bias_blocks, 256, 0, st>>>(
+          static_cast<const float*>(dy), static_cast<const float*>(ymask), ldy, Cout, npix,
+          p.bias_per, bpart);
+    else
+      k_bias_partial<uint16_t><<<(unsigned)p.bias_blocks, 256, 0, st>>>(
+          static_cast<const uint16_t*>(dy), static_cast<const uint16_t*>(ymask), ldy, Cout, npix,
+          p.bias_per, bpart);
+    k_bias_reduce<<<(Cout + 255) / 256, 256, 0, st>>>(bpart, (int)p.bias_blocks, Cout, db);
+  }
   APS_LAUNCH_CHECK();
   return APS_OK;
 }

@@ -5,89 +5,22 @@
 //   T: kt gather of the warped previous output, level 0 only (eq. app-recon-full)
 // Neighbourhoods are staged in LDS with their halos (edge-clamped); each thread owns one
 // output pixel and holds its logits in registers.
-#include "aps_common.h"
+#include "filter_common.h"
 
 using namespace aps;
+using namespace aps::flt;
 
 namespace {
 
-constexpr int TW = 32, TH = 8;  // output tile (256 threads, one pixel each)
-
-struct LevelArgs {
-  const float4* L;      // level input [N, H, W]
-  const void* logits;   // [N, H, W, kstride]
-  int kstride;
-  const float4* coarse; // reconstructed level l+1 [N, H/2, W/2]
-  const float4* prev;   // previous output at level-0 resolution
-  const float2* mv;
-  float4* out;          // [N, H, W]
-  int H, W;
-  int eval_g, eval_u, eval_t, accumulate;
-};
-
-// Logits are read as whole 16-byte vectors: NKP = K rounded up to 4 (f32) or 8 (bf16)
-// values, all inside the pixel's kstride (a multiple of the vector width).
-template <typename LT>
-struct LogitVec;
-template <>
-struct LogitVec<float> {
-  static constexpr int kW = 4;
-  template <int NKP>
-  static __device__ inline void load(const float* p, float* z) {
-#pragma unroll
-    for (int k = 0; k < NKP; k += 4) {
-      const float4 v = *reinterpret_cast<const float4*>(p + k);
-      z[k] = v.x;
-      z[k + 1] = v.y;
-      z[k + 2] = v.z;
-      z[k + 3] = v.w;
-    }
-  }
-};
-template <>
-struct LogitVec<uint16_t> {
-  static constexpr int kW = 8;
-  template <int NKP>
-  static __device__ inline void load(const uint16_t* p, float* z) {
-#pragma unroll
-    for (int k = 0; k < NKP; k += 8) {
-      const u16x8 v = *reinterpret_cast<const u16x8*>(p + k);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) z[k + e] = bf2f(v[e]);
-    }
-  }
-};
-
-__device__ inline float4 warp_at(const float4* __restrict__ prev, const float2* __restrict__ mv,
-                                 int H, int W, int n, int x, int y) {
-  const float2 m = mv[((size_t)n * H + y) * W + x];
-  const float fxf = floorf(m.x), fyf = floorf(m.y);
-  const float fx = m.x - fxf, fy = m.y - fyf;
-  const int x0 = x + (int)fxf, y0 = y + (int)fyf;
-  const int xa = min(max(x0, 0), W - 1), xb = min(max(x0 + 1, 0), W - 1);
-  const int ya = min(max(y0, 0), H - 1), yb = min(max(y0 + 1, 0), H - 1);
-  const float4* P = prev + (size_t)n * H * W;
-  const float4 a = P[(size_t)ya * W + xa], b = P[(size_t)ya * W + xb];
-  const float4 c = P[(size_t)yb * W + xa], d = P[(size_t)yb * W + xb];
-  const float gx = 1.f - fx, gy = 1.f - fy;
-  return make_float4(gy * (gx * a.x + fx * b.x) + fy * (gx * c.x + fx * d.x),
-                     gy * (gx * a.y + fx * b.y) + fy * (gx * c.y + fx * d.y),
-                     gy * (gx * a.z + fx * b.z) + fy * (gx * c.z + fx * d.z), 0.f);
-}
-
 template <int KD, int KU, int KT, bool HU, bool HT, typename LT>
 __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
-  constexpr int RD = KD / 2, RT = KT / 2;
-  constexpr int ND = KD * KD, NU = HU ? KU * KU : 0, NT = HT ? KT * KT : 0;
-  constexpr int NK = ND + NU + NT;
+  using G = Geo<KD, KU, KT, HU, HT>;
+  constexpr int NK = G::NK;
   constexpr int VW = LogitVec<LT>::kW;
   constexpr int NKP = (NK + VW - 1) / VW * VW;
-  constexpr int LW = TW + 2 * RD, LH = TH + 2 * RD;
-  constexpr int CW = TW / 2 + 2, CH = TH / 2 + 2;
-  constexpr int PW = TW + 2 * RT, PH = TH + 2 * RT;
-  __shared__ float4 Ls[LH * LW];
-  __shared__ float4 Cs[HU ? CH * CW : 1];
-  __shared__ float4 Ts[HT ? PH * PW : 1];
+  __shared__ float4 Ls[G::LS];
+  __shared__ float4 Cs[G::CS];
+  __shared__ float4 Ts[G::PS];
 
   const int H = a.H, W = a.W;
   const int tid = threadIdx.x, tx = tid % TW, ty = tid / TW;
@@ -100,31 +33,7 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
     const LT* lp = static_cast<const LT*>(a.logits) + (((size_t)n * H + y) * W + x) * a.kstride;
     LogitVec<LT>::template load<NKP>(lp, z);
   }
-  if (a.eval_g) {
-    const float4* Ln = a.L + (size_t)n * H * W;
-    for (int k = tid; k < LH * LW; k += 256) {
-      const int r = k / LW, c = k % LW;
-      const int yy = min(max(y0 - RD + r, 0), H - 1), xx = min(max(x0 - RD + c, 0), W - 1);
-      Ls[k] = Ln[(size_t)yy * W + xx];
-    }
-  }
-  const int cy0 = y0 / 2 - 1, cx0 = x0 / 2 - 1;
-  if (HU && a.eval_u) {
-    const int Hc = H / 2, Wc = W / 2;
-    const float4* Cn = a.coarse + (size_t)n * Hc * Wc;
-    for (int k = tid; k < CH * CW; k += 256) {
-      const int r = k / CW, c = k % CW;
-      const int yy = min(max(cy0 + r, 0), Hc - 1), xx = min(max(cx0 + c, 0), Wc - 1);
-      Cs[k] = Cn[(size_t)yy * Wc + xx];
-    }
-  }
-  if (HT && a.eval_t) {
-    for (int k = tid; k < PH * PW; k += 256) {
-      const int r = k / PW, c = k % PW;
-      const int yy = min(max(y0 - RT + r, 0), H - 1), xx = min(max(x0 - RT + c, 0), W - 1);
-      Ts[k] = warp_at(a.prev, a.mv, H, W, n, xx, yy);
-    }
-  }
+  stage_tiles<G>(a, Ls, Cs, Ts, x0, y0, n, HU, HT);
   __syncthreads();
   if (!in) return;
 
@@ -138,57 +47,11 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
     sum += z[k];
   }
   float ax = 0.f, ay = 0.f, az = 0.f;
-  if (a.eval_g) {
-#pragma unroll
-    for (int dy = -RD; dy <= RD; ++dy)
-#pragma unroll
-      for (int dx = -RD; dx <= RD; ++dx) {
-        const float w = z[(dy + RD) * KD + (dx + RD)];
-        const float4 v = Ls[(ty + RD + dy) * LW + (tx + RD + dx)];
-        ax += w * v.x;
-        ay += w * v.y;
-        az += w * v.z;
-      }
-  }
-  if (HU && a.eval_u) {
-    if (KU == 2) {
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const float w = z[ND + j * 2 + i];
-          const float4 v = Cs[((y + j) / 2 - cy0) * CW + ((x + i) / 2 - cx0)];
-          ax += w * v.x;
-          ay += w * v.y;
-          az += w * v.z;
-        }
-    } else {
-      constexpr int RU = KU / 2;
-      const int py = y / 2 - cy0, px = x / 2 - cx0;
-#pragma unroll
-      for (int dy = -RU; dy <= RU; ++dy)
-#pragma unroll
-        for (int dx = -RU; dx <= RU; ++dx) {
-          const float w = z[ND + (dy + RU) * KU + (dx + RU)];
-          const float4 v = Cs[(py + dy) * CW + (px + dx)];
-          ax += w * v.x;
-          ay += w * v.y;
-          az += w * v.z;
-        }
-    }
-  }
-  if (HT && a.eval_t) {
-#pragma unroll
-    for (int dy = -RT; dy <= RT; ++dy)
-#pragma unroll
-      for (int dx = -RT; dx <= RT; ++dx) {
-        const float w = z[ND + NU + (dy + RT) * KT + (dx + RT)];
-        const float4 v = Ts[(ty + RT + dy) * PW + (tx + RT + dx)];
-        ax += w * v.x;
-        ay += w * v.y;
-        az += w * v.z;
-      }
-  }
+  for_each_tap<KD, KU, KT, HU, HT>(a, Ls, Cs, Ts, tx, ty, x, y, x0, y0, [&](int k, float4 v) {
+    ax += z[k] * v.x;
+    ay += z[k] * v.y;
+    az += z[k] * v.z;
+  });
   const float inv = 1.f / sum;
   float4 o = make_float4(ax * inv, ay * inv, az * inv, 0.f);
   float4* dst = a.out + ((size_t)n * H + y) * W + x;
@@ -222,23 +85,18 @@ int launch_level_d(const LevelArgs& a, int KD, int KU, int KT, bool hu, bool ht,
   return APS_ERR_UNSUPPORTED;
 }
 
+}  // namespace
+
+namespace aps {
+namespace flt {
 int launch_level(const LevelArgs& a, int dtype, int KD, int KU, int KT, bool hu, bool ht, int N,
                  hipStream_t st) {
   if (dtype == APS_F32) return launch_level_d<float>(a, KD, KU, KT, hu, ht, N, st);
   if (dtype == APS_BF16) return launch_level_d<uint16_t>(a, KD, KU, KT, hu, ht, N, st);
   return APS_ERR_UNSUPPORTED;
 }
-
-bool kstride_ok(int kstride, int K, int dtype) {
-  const int vw = dtype == APS_BF16 ? 8 : 4;
-  return kstride >= K && kstride % vw == 0;
-}
-
-int level_k(int l, int levels, int KD, int KU, int KT, bool temporal) {
-  return KD * KD + (l < levels - 1 ? KU * KU : 0) + (l == 0 && temporal ? KT * KT : 0);
-}
-
-}  // namespace
+}  // namespace flt
+}  // namespace aps
 
 extern "C" {
 

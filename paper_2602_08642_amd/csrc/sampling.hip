@@ -354,6 +354,211 @@ __global__ __launch_bounds__(256) void k_features(int kind, const float* __restr
     if (c < C) store_feat<T>(dst, c, f[c]);
 }
 
+// ======================================================================== backward
+// ------------------------------------------------------------------ scatter + pyramid
+// L0 = (base + w r) / s with w = 1 (hard) or h * clamp(lambda (p - u) / p, 0, 1) (relaxed),
+// p = s - floor(s):  dL0/ds = -L0 / s + (r / s) dw/dp,  dw/dp = h lambda u / p^2 inside the
+// ramp and 0 on its clamped parts and in hard mode.  The pyramid levels are block means of L0,
+// so dLoss/dL0 collects dLoss/dL^l / 4^l from every ancestor.
+struct GradLevels {
+  const float4* p[APS_MAX_LEVELS];
+};
+
+__global__ __launch_bounds__(256) void k_scatter_bwd(const float* __restrict__ s,
+                                                     const uint8_t* __restrict__ count,
+                                                     const int32_t* __restrict__ pixel_offset,
+                                                     const float4* __restrict__ samples,
+                                                     int64_t n_samples, int N, int H, int W,
+                                                     int levels, int relaxed, float lam, float hfac,
+                                                     uint64_t seed, uint32_t frame, GradLevels g,
+                                                     float* __restrict__ grad_s, int accumulate) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)N * H * W) return;
+  const int x = (int)(i % W), y = (int)((i / W) % H), n = (int)(i / ((size_t)W * H));
+  float4 ge = g.p[0][i];
+  float sc = 1.f;
+  for (int l = 1; l < levels; ++l) {
+    sc *= 0.25f;
+    const int Hl = H >> l, Wl = W >> l;
+    const float4 v = g.p[l][((size_t)n * Hl + (y >> l)) * Wl + (x >> l)];
+    ge.x += sc * v.x;
+    ge.y += sc * v.y;
+    ge.z += sc * v.z;
+  }
+  const float si = s[i];
+  float out = 0.f;
+  if (si > 0.f) {
+    const int c = count[i];
+    const int off = pixel_offset[i];
+    const float fl = floorf(si);
+    const int nb = min(c, (int)fl);
+    const int lim = (int)min((int64_t)c, max((int64_t)0, n_samples - off));
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    for (int j = 0; j < min(nb, lim); ++j) {
+      const float4 v = samples[off + j];
+      ax += v.x;
+      ay += v.y;
+      az += v.z;
+    }
+    float dwdp = 0.f;
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c > nb && nb < lim) {
+      r = samples[off + nb];
+      float w = 1.f;
+      if (relaxed) {
+        const float p = si - fl;
+        const float u = uniform24(seed, (uint32_t)i, frame);
+        const float t = lam * (p - u) / p;
+        w = hfac * fminf(fmaxf(t, 0.f), 1.f);
+        if (t > 0.f && t < 1.f) dwdp = hfac * lam * u / (p * p);
+      }
+      ax += w * r.x;
+      ay += w * r.y;
+      az += w * r.z;
+    }
+    const float inv = 1.f / si;
+    const float lx = ax * inv, ly = ay * inv, lz = az * inv;
+    out = ge.x * (dwdp * r.x * inv - lx * inv) + ge.y * (dwdp * r.y * inv - ly * inv) +
+          ge.z * (dwdp * r.z * inv - lz * inv);
+  }
+  grad_s[i] = (accumulate ? grad_s[i] : 0.f) + out;
+}
+
+// ------------------------------------------------------------------ normalisation
+// s = c0 + c1 * sm(z):  dLoss/dz_j = c1 sm_j (g_j - sum_i sm_i g_i); the sum is a fixed tree.
+__global__ __launch_bounds__(256) void k_norm_gdot_partial(const float* __restrict__ z,
+                                                           const float* __restrict__ g, int npx,
+                                                           int nb, const float2* __restrict__ stats,
+                                                           float* __restrict__ part) {
+  const int n = blockIdx.y, b = blockIdx.x;
+  const float2 ms = stats[n];
+  const float inv = 1.f / ms.y;
+  float acc = 0.f;
+  for (int k = 0; k < kNormElems / 256; ++k) {
+    const int i = b * kNormElems + k * 256 + threadIdx.x;
+    if (i < npx) acc += expf(z[(size_t)n * npx + i] - ms.x) * inv * g[(size_t)n * npx + i];
+  }
+  __shared__ float red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)n * nb + b] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_norm_gdot_combine(const float* __restrict__ part, int nb,
+                                                           float* __restrict__ dots) {
+  const int n = blockIdx.x;
+  float acc = 0.f;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[(size_t)n * nb + b];
+  __shared__ float red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) dots[n] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_norm_bwd_apply(const float* __restrict__ z,
+                                                        const float* __restrict__ g, int npx,
+                                                        const float2* __restrict__ stats,
+                                                        const float* __restrict__ dots, float c1,
+                                                        float* __restrict__ gz) {
+  const int n = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= npx) return;
+  const size_t k = (size_t)n * npx + i;
+  const float2 ms = stats[n];
+  const float sm = expf(z[k] - ms.x) / ms.y;
+  gz[k] = c1 * sm * (g[k] - dots[n]);
+}
+
+// ------------------------------------------------------------------ feature assembly
+__device__ inline float dtau_eval(float x) {
+  const float s = 0.5f, h = 0.5f;
+  if (x < s - 1.f) return 0.5f * expf((x + 1.f - s) / s);
+  if (x < 1.f - h) return 0.5f;
+  return 0.5f * expf(-(x + h - 1.f) / h);
+}
+__device__ inline float dsrgb(float v) {
+  if (v <= 0.f || v >= 1.f) return v <= 0.0031308f ? 12.92f : 0.f;
+  return v <= 0.0031308f ? 12.92f : (1.055f / 2.4f) * powf(v, 1.f / 2.4f - 1.f);
+}
+__device__ inline float dtonemap_eval(float L) {
+  if (!(L > 0.f)) return 0.f;
+  const float x = 0.4f * logf(L + 1e-4f);
+  return dsrgb(tau_eval(x)) * dtau_eval(x) * 0.4f / (L + 1e-4f);
+}
+
+__device__ inline void splat_prev(float* __restrict__ gprev, int H, int W, int n, int x, int y,
+                                  float2 m, float gx_, float gy_, float gz_) {
+  const float fxf = floorf(m.x), fyf = floorf(m.y);
+  const float fx = m.x - fxf, fy = m.y - fyf, gx = 1.f - fx, gy = 1.f - fy;
+  const int x0 = x + (int)fxf, y0 = y + (int)fyf;
+  const int xa = min(max(x0, 0), W - 1), xb = min(max(x0 + 1, 0), W - 1);
+  const int ya = min(max(y0, 0), H - 1), yb = min(max(y0 + 1, 0), H - 1);
+  const int idx[4] = {ya * W + xa, ya * W + xb, yb * W + xa, yb * W + xb};
+  const float wt[4] = {gy * gx, gy * fx, fy * gx, fy * fx};
+  float* P = gprev + (size_t)n * H * W * 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (wt[k] == 0.f) continue;
+    float* d = P + (size_t)idx[k] * 4;
+    atomicAdd(d + 0, wt[k] * gx_);
+    atomicAdd(d + 1, wt[k] * gy_);
+    atomicAdd(d + 2, wt[k] * gz_);
+  }
+}
+
+template <typename T>
+__device__ inline float load_feat(const T* p, int c);
+template <>
+__device__ inline float load_feat<float>(const float* p, int c) { return p[c]; }
+template <>
+__device__ inline float load_feat<uint16_t>(const uint16_t* p, int c) { return bf2f(p[c]); }
+
+// Transpose of k_features: adds to grad_L0 (RGB), grad_s, and (atomically) grad_prev.
+template <typename T>
+__global__ __launch_bounds__(256) void k_features_bwd(int kind, const float4* __restrict__ L0,
+                                                      const float4* __restrict__ prev,
+                                                      const float2* __restrict__ mv, int N, int H,
+                                                      int W, int C, const T* __restrict__ gfeat,
+                                                      float4* __restrict__ gL0,
+                                                      float* __restrict__ gs,
+                                                      float* __restrict__ gprev) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)N * H * W) return;
+  const int x = (int)(i % W), y = (int)((i / W) % H), n = (int)(i / ((size_t)W * H));
+  const T* g = gfeat + i * C;
+  int o = 7;
+  if (kind == 1) {
+    const float4 l = L0[i];
+    if (gL0) {
+      float4 a = gL0[i];
+      a.x += load_feat<T>(g, 7) / (1.f + fabsf(l.x));
+      a.y += load_feat<T>(g, 8) / (1.f + fabsf(l.y));
+      a.z += load_feat<T>(g, 9) / (1.f + fabsf(l.z));
+      gL0[i] = a;
+    }
+    if (gs) gs[i] += load_feat<T>(g, 10);
+    o = 11;
+  }
+  if (prev && gprev) {
+    const float2 m = mv[i];
+    const float4 w = warp_sample(prev, H, W, n, x, y, m);
+    float d0, d1, d2;
+    if (kind == 0) {
+      d0 = dtonemap_eval(w.x);
+      d1 = dtonemap_eval(w.y);
+      d2 = dtonemap_eval(w.z);
+    } else {
+      d0 = 1.f / (1.f + fabsf(w.x));
+      d1 = 1.f / (1.f + fabsf(w.y));
+      d2 = 1.f / (1.f + fabsf(w.z));
+    }
+    splat_prev(gprev, H, W, n, x, y, m, load_feat<T>(g, o) * d0, load_feat<T>(g, o + 1) * d1,
+               load_feat<T>(g, o + 2) * d2);
+  }
+}
+
 }  // namespace
 
 // ======================================================================== C ABI
@@ -492,6 +697,111 @@ int aps_assemble_features(int kind, const float* aux, const float* L0, const flo
   else if (out_dtype == APS_BF16)
     k_features<uint16_t><<<blocks, 256, 0, st>>>(kind, aux, L4, s, P4, M2, N, H, W, C,
                                                  static_cast<uint16_t*>(out));
+  else
+    return APS_ERR_UNSUPPORTED;
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================== backward C ABI
+extern "C" {
+
+int aps_scatter_samples_bwd(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                            const float* samples, int64_t n_samples, int N, int H, int W,
+                            int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
+                            const float* const* grad_L, float* grad_s, int accumulate,
+                            void* stream) {
+  if (n_samples < 0) return APS_ERR_SHAPE;
+  if (levels < 1 || levels > APS_MAX_LEVELS) return APS_ERR_UNSUPPORTED;
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if (mode != APS_HARD && mode != APS_RELAXED) return APS_ERR_ARG;
+  if (mode == APS_RELAXED && !(lambda >= 1.f)) return APS_ERR_ARG;
+  const int div = 1 << (levels - 1);
+  if (H % div || W % div) return APS_ERR_SHAPE;
+  const size_t npix = (size_t)N * H * W;
+  if (npix > 0x7fffffffull) return APS_ERR_SHAPE;
+  if (npix == 0) return APS_OK;
+  if (!s || !count || !pixel_offset || !grad_L || !grad_s || (!samples && n_samples > 0))
+    return APS_ERR_NULL;
+  GradLevels g{};
+  for (int l = 0; l < levels; ++l) {
+    if (!grad_L[l]) return APS_ERR_NULL;
+    g.p[l] = reinterpret_cast<const float4*>(grad_L[l]);
+  }
+  const float hfac = 2.f * lambda / (2.f * lambda - 1.f);
+  k_scatter_bwd<<<(unsigned)((npix + 255) / 256), 256, 0, as_stream(stream)>>>(
+      s, count, pixel_offset, reinterpret_cast<const float4*>(samples), n_samples, N, H, W, levels,
+      mode == APS_RELAXED, lambda, hfac, seed, frame, g, grad_s, accumulate);
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+size_t aps_normalize_bwd_workspace_size(int N, int H, int W) {
+  const int npx = H * W;
+  const int nb = (npx + kNormElems - 1) / kNormElems;
+  return (size_t)N * nb * sizeof(float2) + (size_t)N * sizeof(float2) + (size_t)N * nb * 4 +
+         (size_t)N * 4 + 1024;
+}
+
+int aps_normalize_density_bwd(const float* z, int N, int H, int W, float budget_spp,
+                              float uniform_frac, const float* grad_s, float* grad_z, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!z || !grad_s || !grad_z) return APS_ERR_NULL;
+  if (!(budget_spp > 0.f) || !(uniform_frac >= 0.f && uniform_frac <= 1.f)) return APS_ERR_ARG;
+  if ((size_t)H * W > 0x7fffffffull) return APS_ERR_SHAPE;
+  if (!ws || ws_bytes < aps_normalize_bwd_workspace_size(N, H, W)) return APS_ERR_WORKSPACE;
+  const int npx = H * W;
+  const int nb = (npx + kNormElems - 1) / kNormElems;
+  char* p = static_cast<char*>(ws);
+  float2* part = reinterpret_cast<float2*>(p);
+  p += (((size_t)N * nb * sizeof(float2)) + 255) / 256 * 256;
+  float2* stats = reinterpret_cast<float2*>(p);
+  p += (((size_t)N * sizeof(float2)) + 255) / 256 * 256;
+  float* gpart = reinterpret_cast<float*>(p);
+  p += (((size_t)N * nb * 4) + 255) / 256 * 256;
+  float* dots = reinterpret_cast<float*>(p);
+  hipStream_t st = as_stream(stream);
+  k_norm_partial<<<dim3(nb, N), 256, 0, st>>>(z, npx, nb, part);
+  k_norm_combine<<<N, 256, 0, st>>>(part, nb, stats);
+  k_norm_gdot_partial<<<dim3(nb, N), 256, 0, st>>>(z, grad_s, npx, nb, stats, gpart);
+  k_norm_gdot_combine<<<N, 256, 0, st>>>(gpart, nb, dots);
+  const float c1 = (1.f - uniform_frac) * budget_spp * (float)npx;
+  k_norm_bwd_apply<<<dim3((npx + 255) / 256, N), 256, 0, st>>>(z, grad_s, npx, stats, dots, c1,
+                                                               grad_z);
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+int aps_assemble_features_bwd(int kind, const float* L0, const float* prev, const float* mv,
+                              int N, int H, int W, int C, int feat_dtype, const void* grad_feat,
+                              float* grad_L0, float* grad_s, float* grad_prev, void* stream) {
+  if (kind != APS_FEAT_SAMPLER && kind != APS_FEAT_KERNEL) return APS_ERR_ARG;
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!grad_feat) return APS_ERR_NULL;
+  if (kind == APS_FEAT_KERNEL && !L0) return APS_ERR_NULL;
+  if (prev && !mv) return APS_ERR_NULL;
+  const int need = (kind == APS_FEAT_KERNEL ? 11 : 7) + (prev ? 4 : 0);
+  if (C < need || C > 16) return APS_ERR_SHAPE;
+  const size_t npix = (size_t)N * H * W;
+  const unsigned blocks = (unsigned)((npix + 255) / 256);
+  hipStream_t st = as_stream(stream);
+  const float4* L4 = reinterpret_cast<const float4*>(L0);
+  const float4* P4 = reinterpret_cast<const float4*>(prev);
+  const float2* M2 = reinterpret_cast<const float2*>(mv);
+  float4* G4 = reinterpret_cast<float4*>(grad_L0);
+  if (feat_dtype == APS_F32)
+    k_features_bwd<float><<<blocks, 256, 0, st>>>(kind, L4, P4, M2, N, H, W, C,
+                                                  static_cast<const float*>(grad_feat), G4, grad_s,
+                                                  grad_prev);
+  else if (feat_dtype == APS_BF16)
+    k_features_bwd<uint16_t><<<blocks, 256, 0, st>>>(kind, L4, P4, M2, N, H, W, C,
+                                                     static_cast<const uint16_t*>(grad_feat), G4,
+                                                     grad_s, grad_prev);
   else
     return APS_ERR_UNSUPPORTED;
   APS_LAUNCH_CHECK();

@@ -1,0 +1,106 @@
+"""Learned density vs uniform sampling at equal spp, and the equal-error budget ratio.
+
+    python -m paper_2602_08642_amd.evaluate --steps 300 --out results.json [--save weights.npz]
+
+Three reconstructions on held-out procedural clips (scene seeds disjoint from training):
+  learned   sampler CNN + kernel U-Net trained jointly (relaxed stochastic rounding)
+  uniform   s = B everywhere, kernel U-Net trained with uniform sampling ("Ours Uniform")
+  fallback  s = B everywhere, all-zero logits (box-weighted pyramid), no training
+Then the uniform variant is evaluated at larger budgets; the budget at which it matches the
+learned variant's error at B (linear interpolation of PSNR in the budget) gives the sample
+saving at equal error.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import pipeline, train
+
+
+def save_weights(path, dnet, knet_l, knet_u):
+    arrs = {}
+    for tag, net in (("density", dnet), ("kernel_learned", knet_l), ("kernel_uniform", knet_u)):
+        if net is None:
+            continue
+        for name, (w, b) in net.weights().items():
+            arrs[f"{tag}/{name}/w"] = w
+            arrs[f"{tag}/{name}/b"] = b
+    np.savez_compressed(path, **arrs)
+
+
+def load_weights(path):
+    z = np.load(path)
+    out = {}
+    for key in z.files:
+        tag, name, kind = key.split("/")
+        d = out.setdefault(tag, {})
+        w, b = d.get(name, (None, None))
+        d[name] = (z[key], b) if kind == "w" else (w, z[key])
+    return out
+
+
+def run(steps=300, batch=4, frames=8, lr=1e-3, eval_seeds=tuple(range(10000, 10008)),
+        budgets=(0.25, 0.3, 0.35, 0.4, 0.5), device="cuda", cfg_name="c4", log=print, H=None):
+    cfg = pipeline.CONFIGS[cfg_name]
+    if H is not None:
+        cfg = dataclasses.replace(cfg, H=H, W=H)
+    res = {"config": cfg_name, "H": cfg.H, "W": cfg.W, "budget": cfg.budget, "steps": steps,
+           "batch": batch, "frames": frames}
+    t0 = time.time()
+    dnet, knet_l, hist_l = train.train(cfg, train.TrainConfig(steps=steps, batch=batch, frames=frames, lr=lr),
+                                       device, log=lambda m: log("[learned] " + m))
+    res["train_learned_s"] = round(time.time() - t0, 1)
+    t1 = time.time()
+    _, knet_u, hist_u = train.train(cfg, train.TrainConfig(steps=steps, batch=batch, frames=frames, lr=lr,
+                                                           uniform=True),
+                                    device, log=lambda m: log("[uniform] " + m))
+    res["train_uniform_s"] = round(time.time() - t1, 1)
+    res["loss_learned"] = [hist_l[0]["loss"], float(np.mean([h["loss"] for h in hist_l[-10:]]))]
+    res["loss_uniform"] = [hist_u[0]["loss"], float(np.mean([h["loss"] for h in hist_u[-10:]]))]
+    seeds = list(eval_seeds)
+    res["learned"] = train.evaluate(cfg, dnet, knet_l, seeds, frames, device)
+    res["uniform"] = train.evaluate(cfg, None, knet_u, seeds, frames, device, uniform=True)
+    res["fallback"] = train.evaluate(cfg, None, None, seeds, frames, device, uniform=True)
+    sweep = [train.evaluate(cfg, None, knet_u, seeds, frames, device, uniform=True, budget=b)
+             for b in budgets]
+    res["uniform_budget_sweep"] = sweep
+    target = res["learned"]["psnr"]
+    eq = None
+    for a, b in zip(sweep[:-1], sweep[1:]):
+        if a["psnr"] <= target <= b["psnr"] and b["psnr"] > a["psnr"]:
+            f = (target - a["psnr"]) / (b["psnr"] - a["psnr"])
+            eq = a["budget"] + f * (b["budget"] - a["budget"])
+            break
+    res["equal_error_uniform_budget"] = eq
+    res["equal_error_sample_ratio"] = None if eq is None else eq / cfg.budget
+    res["psnr_gain_db"] = res["learned"]["psnr"] - res["uniform"]["psnr"]
+    return res, (dnet, knet_l, knet_u)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--frames", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--size", type=int, default=None)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--save", default=None)
+    a = ap.parse_args()
+    res, nets = run(a.steps, a.batch, a.frames, a.lr, H=a.size, log=lambda m: print(m, flush=True))
+    print(json.dumps(res))
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+    if a.save:
+        save_weights(a.save, *nets)
+
+
+if __name__ == "__main__":
+    main()

@@ -294,3 +294,168 @@ def upsample(coarse, logits, KD, KU, KT, has_temporal: bool, accum=None):
                                   KU, KT, int(has_temporal), N, H, W, _p(accum), _stream()),
             "upsample")
     return accum
+
+
+# ------------------------------------------------------------------ backward (a10)
+
+def denoise_pyramid_bwd(Ls, logits, KD: int, KU: int, KT: int, prev, mv, grad_out,
+                        grad_dtype=None, want_prev: bool = True):
+    """-> (grad_logits list [same shape as logits], grad_L list, grad_prev or None)."""
+    levels = len(Ls)
+    L0 = _need(Ls[0], "L0", _F32)
+    _need(grad_out, "grad_out", _F32)
+    N, H, W, _ = L0.shape
+    ldt = logits[0].dtype
+    gdt = grad_dtype or ldt
+    glog = [torch.empty(t.shape, dtype=gdt, device=t.device) for t in logits]
+    gL = [torch.empty_like(t) for t in Ls]
+    gprev = torch.zeros_like(prev) if (prev is not None and want_prev) else None
+    lib = L.load()
+    nb = lib.aps_denoise_pyramid_bwd_workspace_size(N, H, W, levels, KD, KU, KT, int(prev is not None))
+    ws = WS.get(nb, L0.device)
+    arr = lambda ts: (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in ts])
+    ka = (C.c_int * L.APS_MAX_LEVELS)(*[t.shape[-1] for t in logits])
+    L.check(lib.aps_denoise_pyramid_bwd(arr(Ls), arr(logits), _dt(ldt), ka, levels, KD, KU, KT,
+                                        _p(prev), _p(mv), N, H, W, _p(grad_out), arr(glog),
+                                        _dt(gdt), ka, arr(gL), _p(gprev), _p(ws), nb, _stream()),
+            "denoise_pyramid_bwd")
+    return glog, gL, gprev
+
+
+def scatter_samples_bwd(s, count, pixel_offset, samples, grad_L, mode="relaxed", lam=10.0,
+                        seed=0, frame=0, grad_s=None):
+    _need(s, "s", _F32)
+    N, H, W = s.shape
+    acc = grad_s is not None
+    if grad_s is None:
+        grad_s = torch.empty_like(s)
+    arr = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in grad_L])
+    m = L.APS_HARD if mode == "hard" else L.APS_RELAXED
+    L.check(L.load().aps_scatter_samples_bwd(_p(s), _p(count), _p(pixel_offset), _p(samples),
+                                             samples.shape[0], N, H, W, len(grad_L), m, lam, seed,
+                                             frame, arr, _p(grad_s), int(acc), _stream()),
+            "scatter_samples_bwd")
+    return grad_s
+
+
+def normalize_density_bwd(z, budget, grad_s, uniform_frac=1.0 / 8.0):
+    _need(z, "z", _F32)
+    _need(grad_s, "grad_s", _F32)
+    N, H, W = z.shape
+    gz = torch.empty_like(z)
+    lib = L.load()
+    nb = lib.aps_normalize_bwd_workspace_size(N, H, W)
+    ws = WS.get(nb, z.device)
+    L.check(lib.aps_normalize_density_bwd(_p(z), N, H, W, budget, uniform_frac, _p(grad_s),
+                                          _p(gz), _p(ws), nb, _stream()), "normalize_density_bwd")
+    return gz
+
+
+def assemble_features_bwd(kind, grad_feat, L0=None, prev=None, mv=None, grad_L0=None,
+                          grad_s=None, grad_prev=None):
+    _need(grad_feat, "grad_feat")
+    N, H, W, Cf = grad_feat.shape
+    k = L.APS_FEAT_SAMPLER if kind == "sampler" else L.APS_FEAT_KERNEL
+    L.check(L.load().aps_assemble_features_bwd(k, _p(L0), _p(prev), _p(mv), N, H, W, Cf,
+                                               _dt(grad_feat.dtype), _p(grad_feat), _p(grad_L0),
+                                               _p(grad_s), _p(grad_prev), _stream()),
+            "assemble_features_bwd")
+
+
+def copy_channels(src, dst_dtype, dst_ld, C_copy=None):
+    """[..., src_ld] -> [..., dst_ld] in dst_dtype, first C_copy channels copied, rest zero."""
+    _need(src, "src")
+    src_ld = src.shape[-1]
+    C_copy = src_ld if C_copy is None else C_copy
+    npix = src.numel() // src_ld
+    out = torch.empty(tuple(src.shape[:-1]) + (dst_ld,), dtype=dst_dtype, device=src.device)
+    L.check(L.load().aps_copy_channels(_p(src), _dt(src.dtype), src_ld, _p(out), _dt(dst_dtype),
+                                       dst_ld, npix, C_copy, _stream()), "copy_channels")
+    return out
+
+
+def scale_by(x, scale):
+    _need(x, "x", _F32)
+    _need(scale, "scale", _F32)
+    L.check(L.load().aps_scale_by(_p(x), x.numel(), _p(scale), _stream()), "scale_by")
+    return x
+
+
+def pack_dgrad(layer_spec, w_master, dtype):
+    lib = L.load()
+    n = lib.aps_conv_packed_elems(layer_spec["cin"], layer_spec["k"], layer_spec["cout"])
+    pk = torch.empty(n, dtype=dtype, device=w_master.device)
+    L.check(lib.aps_conv_pack_weights_dgrad(_p(w_master), layer_spec["cout"], layer_spec["k"],
+                                            layer_spec["cin"], _dt(dtype), _p(pk), _stream()),
+            "pack_weights_dgrad")
+    return pk
+
+
+def conv2d_bwd(x, x2, mode, layer_spec, packed_T, dy, ymask=None, need_dx=True, need_dx2=True):
+    """Gradients of one conv layer.  dy [N,H,W,ldy] in the net dtype; ymask = the layer's
+    post-ReLU output (None without ReLU).  -> (dx, dx2, dw [cout,k,k,cin] f32, db [cout] f32)."""
+    _need(dy, "dy", x.dtype)
+    N, H, W, ldy = dy.shape
+    cout, cin, k = layer_spec["cout"], layer_spec["cin"], layer_spec["k"]
+    Cx = x.shape[-1]
+    C2 = x2.shape[-1] if x2 is not None else 0
+    m = {"direct": L.APS_CONV_DIRECT, "pool2": L.APS_CONV_POOL2, "up2cat": L.APS_CONV_UP2_CAT}[mode]
+    lib = L.load()
+    dx = dx2 = None
+    if need_dx or (need_dx2 and x2 is not None):
+        dX = torch.empty((N, H, W, cin), dtype=x.dtype, device=x.device)
+        L.check(lib.aps_conv2d_bwd_data(_p(dy), _p(ymask), ldy, N, H, W, cout, _p(packed_T), k, cin,
+                                        _dt(x.dtype), _p(dX), _stream()), "conv2d_bwd_data")
+        if mode == "direct":
+            dx = dX
+        else:
+            dx = torch.empty_like(x)
+            dx2 = torch.empty_like(x2) if x2 is not None else None
+            L.check(lib.aps_conv_input_grad(m, _p(dX), N, H, W, Cx, C2, _dt(x.dtype), _p(dx), 0,
+                                            _p(dx2), 0, _stream()), "conv_input_grad")
+    dw = torch.empty((cout, k, k, cin), dtype=_F32, device=x.device)
+    db = torch.empty(cout, dtype=_F32, device=x.device)
+    nb = lib.aps_conv2d_bwd_weight_workspace_size(N, H, W, Cx, C2, cout, k)
+    ws = WS.get(nb, x.device)
+    L.check(lib.aps_conv2d_bwd_weight(_p(x), _p(x2), m, N, H, W, Cx, C2, _p(dy), _p(ymask), ldy,
+                                      cout, k, _dt(x.dtype), _p(dw), _p(db), _p(ws), nb, _stream()),
+            "conv2d_bwd_weight")
+    return dx, dx2, dw, db
+
+
+# ------------------------------------------------------------------ training (a11)
+
+def tmo_loss(out, ref, params, prev_out=None, prev_ref=None, mv=None, want_prev=True):
+    """-> (loss [1] device, grad_out, grad_prev or None); params [N,5] (k, alpha, beta, s, h)."""
+    _need(out, "out", _F32)
+    _need(ref, "ref", _F32)
+    _need(params, "params", _F32)
+    N, H, W, _ = out.shape
+    loss = torch.empty(1, dtype=_F32, device=out.device)
+    gout = torch.empty_like(out)
+    gprev = torch.zeros_like(out) if (prev_out is not None and want_prev) else None
+    lib = L.load()
+    nb = lib.aps_tmo_loss_workspace_size(N, H, W)
+    ws = WS.get(nb, out.device)
+    L.check(lib.aps_tmo_loss(_p(out), _p(ref), _p(prev_out), _p(prev_ref), _p(mv), _p(params), N, H,
+                             W, _p(loss), _p(gout), _p(gprev), _p(ws), nb, _stream()), "tmo_loss")
+    return loss, gout, gprev
+
+
+def adamw_step(param, m, v, grad, lr, step, beta1=0.8, beta2=0.985, eps=1e-8, weight_decay=0.02,
+               grad_scale=1.0):
+    for t, nm in ((param, "param"), (m, "m"), (v, "v"), (grad, "grad")):
+        _need(t, nm, _F32)
+    L.check(L.load().aps_adamw_step(_p(param), _p(m), _p(v), _p(grad), param.numel(), lr, beta1,
+                                    beta2, eps, weight_decay, step, grad_scale, _stream()),
+            "adamw_step")
+
+
+def sumsq(x):
+    _need(x, "x", _F32)
+    out = torch.empty(1, dtype=_F32, device=x.device)
+    lib = L.load()
+    nb = lib.aps_sumsq_workspace_size(x.numel())
+    ws = WS.get(nb, x.device)
+    L.check(lib.aps_sumsq(_p(x), x.numel(), _p(out), _p(ws), nb, _stream()), "sumsq")
+    return out

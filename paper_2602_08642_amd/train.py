@@ -1,0 +1,289 @@
+"""Training of the sampler CNN and the kernel-predictor U-Net on frames the pipeline itself
+generates (procedural clips, renderer stand-in), with the library's forward and backward
+kernels behind torch.autograd.Function (Sec. 6.3).
+
+* Relaxed stochastic rounding in training (Sec. 4.3, lambda = 10); the hard mask at test time.
+* Loss per frame: tonemapped max(1.25 temporal, spatial) with randomised filmic parameters.
+* Sliding window of two frames: frame t takes frame t-1's output (with its graph) as history;
+  the gradient of frame t's loss reaches frame t-1's networks but stops there (a gate closes
+  once frame t-1's own loss has been propagated).
+* AdamW, betas (0.8, 0.985), weight decay 0.02, cosine learning-rate decay, fp32 master weights
+  re-packed into the bf16 (or fp32) working copies after every step.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import autograd as ag
+from . import ops
+from .pipeline import FrameConfig, density_spec, kernel_spec
+
+F32 = torch.float32
+
+
+# ------------------------------------------------------------------ data
+
+@dataclasses.dataclass
+class ClipBatch:
+    aux: torch.Tensor     # [T, N, H, W, 8]
+    ref: torch.Tensor     # [T, N, H, W, 4]  noise-free radiance
+    mv: torch.Tensor      # [T, N, H, W, 2]
+    params: torch.Tensor  # [N, 5] tonemapper (k, alpha, beta, s, h)
+    seeds: list
+
+
+def make_clips(seeds, H, W, T, device, randomise_tmo=True, rng_seed=0):
+    import procgen
+    N = len(seeds)
+    aux = np.zeros((T, N, H, W, 8), np.float32)
+    ref = np.zeros((T, N, H, W, 4), np.float32)
+    mv = np.zeros((T, N, H, W, 2), np.float32)
+    prm = np.zeros((N, 5), np.float32)
+    rng = np.random.default_rng([rng_seed, 0x7A0])
+    for n, sd in enumerate(seeds):
+        frames = procgen.make_clip(sd, H, W, T)
+        for t, fr in enumerate(frames):
+            aux[t, n] = fr.aux
+            ref[t, n, ..., :3] = fr.truth
+            mv[t, n] = fr.mv
+        kc = -float(np.median(np.log(np.maximum(frames[0].truth, 0) + 1e-4)))
+        if randomise_tmo:
+            prm[n] = [kc + rng.uniform(-0.5, 0.5), rng.uniform(0.25, 0.6), rng.uniform(0.8, 1.2),
+                      rng.uniform(0.1, 0.9), rng.uniform(0.1, 0.9)]
+        else:
+            prm[n] = [kc, 0.4, 1.0, 0.5, 0.5]
+    d = lambda a: torch.tensor(a, device=device)
+    return ClipBatch(d(aux), d(ref), d(mv), d(prm), list(seeds))
+
+
+def sample_pool(ref_t, gen, J=8):
+    """Renderer stand-in on the device: J noisy samples per pixel, truth * (1 + n),
+    n = lognormal(0, 0.8) - E[lognormal(0, 0.8)] (input generation, not the method)."""
+    N, H, W, _ = ref_t.shape
+    g = torch.randn((N * H * W, J), generator=gen, device=ref_t.device)
+    one_n = torch.exp(0.8 * g) - math.exp(0.32) + 1.0
+    pool = ref_t.reshape(N * H * W, 1, 4) * one_n.unsqueeze(-1)
+    pool[..., 3] = 0
+    return pool.contiguous()
+
+
+# ------------------------------------------------------------------ networks
+
+class TrainNet:
+    def __init__(self, spec, weights, dtype, device):
+        self.spec = [dict(l) for l in spec]
+        self.layers = {}
+        self.state = {}
+        for l in self.spec:
+            w, b = weights[l["name"]]
+            wt = torch.tensor(w, dtype=F32, device=device).requires_grad_(True)
+            bt = torch.tensor(b, dtype=F32, device=device).requires_grad_(True)
+            self.layers[l["name"]] = ag.LayerRef(l, wt, bt, dtype)
+            self.state[l["name"]] = [(torch.zeros_like(wt), torch.zeros_like(wt)),
+                                     (torch.zeros_like(bt), torch.zeros_like(bt))]
+
+    def params(self):
+        for name, lr in self.layers.items():
+            yield name, lr.w, self.state[name][0]
+            yield name, lr.b, self.state[name][1]
+
+    def refresh(self):
+        for lr in self.layers.values():
+            lr.refresh()
+
+    def weights(self):
+        return {n: (lr.w.detach().cpu().numpy(), lr.b.detach().cpu().numpy()) for n, lr in self.layers.items()}
+
+
+def density_forward(net: TrainNet, cfg: FrameConfig, aux, prev, mv):
+    feat = ag.Features.apply("sampler", aux, None, None, prev, mv, cfg.sampler_cin, cfg.net_dtype)
+    L = net.layers
+    h = ag.conv(feat, L["d0"])
+    h = ag.conv(h, L["d1"])
+    z = ag.conv(h, L["d2"], out_dtype=F32, ldy=1)
+    N, H, W, _ = z.shape
+    return ag.Normalize.apply(z.view(N, H, W), cfg.budget, cfg.uniform_frac)
+
+
+def unet_forward(net: TrainNet, cfg: FrameConfig, feat):
+    L = net.layers
+    t = ag.conv(feat, L["enc0a"])
+    e0 = ag.conv(t, L["enc0b"])
+    t = ag.conv(e0, L["enc1a"], "pool2")
+    e1 = ag.conv(t, L["enc1b"])
+    t = ag.conv(e1, L["enc2a"], "pool2")
+    e2 = ag.conv(t, L["enc2b"])
+    t = ag.conv(e2, L["bota"], "pool2")
+    e3 = ag.conv(t, L["botb"])
+    t = ag.conv(e3, L["dec2a"], "up2cat", x2=e2)
+    d2 = ag.conv(t, L["dec2b"])
+    t = ag.conv(d2, L["dec1a"], "up2cat", x2=e1)
+    d1 = ag.conv(t, L["dec1b"])
+    t = ag.conv(d1, L["dec0a"], "up2cat", x2=e0)
+    d0 = ag.conv(t, L["dec0b"])
+    feats = [d0, d1, d2, e3]
+    ks = cfg.head_channels()
+    return [ag.conv(feats[l], L[f"head{l}"], out_dtype=cfg.logit_dtype,
+                    ldy=ops.round_kstride(ks[l], cfg.logit_dtype)) for l in range(cfg.levels)]
+
+
+class _Gate(torch.autograd.Function):
+    """Identity whose backward passes the gradient only while the gate is open."""
+
+    @staticmethod
+    def forward(ctx, x, gate):
+        ctx.gate = gate
+        return x.view_as(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return (g if ctx.gate["open"] else None), None
+
+
+def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relaxed",
+                  uniform=False, lam=10.0):
+    N = aux.shape[0]
+    if uniform or dnet is None:
+        s = torch.full((N, cfg.H, cfg.W), cfg.budget, dtype=F32, device=aux.device)
+    else:
+        s = density_forward(dnet, cfg, aux, prev, mv)
+    cap = int(N * cfg.H * cfg.W * (cfg.budget + 1)) + 1024
+    req = ops.sample_mask(s.detach(), seed, frame, capacity=cap)
+    samples = ops.fixture_render(pool, req["count"], req["pixel_offset"], cap)
+    Ls = ag.Scatter.apply(s, req, samples, cfg.levels, mode, lam, seed, frame)
+    if knet is None:
+        ks = cfg.head_channels()
+        logits = [torch.zeros((N, cfg.H >> l, cfg.W >> l, ops.round_kstride(ks[l], cfg.logit_dtype)),
+                              dtype=cfg.logit_dtype, device=aux.device) for l in range(cfg.levels)]
+    else:
+        feat = ag.Features.apply("kernel", aux, Ls[0], s, prev, mv, cfg.kernel_cin, cfg.net_dtype)
+        logits = unet_forward(knet, cfg, feat)
+    out = ag.denoise(list(Ls), logits, cfg.KD, cfg.KU, cfg.KT, prev, mv)
+    return out, s
+
+
+# ------------------------------------------------------------------ training
+
+@dataclasses.dataclass
+class TrainConfig:
+    steps: int = 200
+    batch: int = 4
+    frames: int = 8
+    lr: float = 1e-3
+    train_density: bool = True
+    uniform: bool = False
+    n_train_clips: int = 64
+    seed: int = 0
+    log_every: int = 10
+
+
+def cosine_lr(step, total, peak):
+    return 0.5 * peak * (1.0 + math.cos(math.pi * min(step, total) / max(total, 1)))
+
+
+def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, kw=None):
+    import procgen
+    dspec, kspec = density_spec(cfg), kernel_spec(cfg)
+    dw = dw or procgen.init_weights(dspec, 7)
+    kw = kw or procgen.init_weights(kspec, 8)
+    dnet = None if tc.uniform else TrainNet(dspec, dw, cfg.net_dtype, device)
+    knet = TrainNet(kspec, kw, cfg.net_dtype, device)
+    nets = [knet] + ([] if dnet is None else [dnet])
+    pool_clips = [list(range(c * tc.batch, (c + 1) * tc.batch)) for c in range(tc.n_train_clips // tc.batch)]
+    data = {}
+    gen = torch.Generator(device=device).manual_seed(tc.seed)
+    history = []
+    t0 = time.time()
+    for step in range(1, tc.steps + 1):
+        ci = (step - 1) % len(pool_clips)
+        if ci not in data:
+            data[ci] = make_clips(pool_clips[ci], cfg.H, cfg.W, tc.frames, device, rng_seed=ci)
+        cb = data[ci]
+        prev, prev_ref, gate = None, None, None
+        losses = []
+        for t in range(tc.frames):
+            pool = sample_pool(cb.ref[t], gen)
+            pin = None if prev is None else _Gate.apply(prev, gate)
+            mv = cb.mv[t] if prev is not None else None
+            seed = 1_000_003 * step + t
+            out, s = frame_forward(dnet, knet, cfg, cb.aux[t], pin, mv, pool, seed, t, "relaxed",
+                                   uniform=tc.uniform)
+            loss = ag.TMOLoss.apply(out, pin, cb.ref[t], prev_ref, mv, cb.params)
+            loss.backward(retain_graph=True)
+            if gate is not None:
+                gate["open"] = False        # frame t-2 stays out of later windows
+            losses.append(loss.detach())
+            prev, prev_ref, gate = out, cb.ref[t], {"open": True}
+        del prev, out, loss, pin
+        # AdamW on the fp32 masters (gradients averaged over the frames)
+        lr = cosine_lr(step - 1, tc.steps, tc.lr)
+        gn = 0.0
+        finite = True
+        for net in nets:
+            for _, p, (m, v) in net.params():
+                if p.grad is None:
+                    continue
+                ss = float(ops.sumsq(p.grad).item())
+                finite &= math.isfinite(ss)
+                gn += ss
+        if finite:
+            for net in nets:
+                for _, p, (m, v) in net.params():
+                    if p.grad is not None:
+                        ops.adamw_step(p.data, m, v, p.grad, lr, step, grad_scale=1.0 / tc.frames)
+                net.refresh()
+        for net in nets:
+            for _, p, _ in net.params():
+                p.grad = None
+        lval = float(torch.stack(losses).mean().item())
+        history.append(dict(step=step, loss=lval, grad_norm=math.sqrt(gn), lr=lr, skipped=not finite))
+        if step % tc.log_every == 0 or step == 1:
+            log(f"step {step:4d} loss {lval:.5f} |g| {math.sqrt(gn):.3e} lr {lr:.2e} "
+                f"{time.time() - t0:.1f}s")
+    return dnet, knet, history
+
+
+# ------------------------------------------------------------------ evaluation
+
+def psnr_tonemapped(out, ref, params):
+    """PSNR of the evaluation-tonemapped images (metric only, computed with the loss kernel's
+    tonemapper via a zero-temporal call is not needed: plain torch on the outputs)."""
+    k, a = params[:, 0].view(-1, 1, 1, 1), params[:, 1].view(-1, 1, 1, 1)
+
+    def tm(x):
+        y = torch.log(torch.clamp(x[..., :3], min=0) + 1e-4)
+        xx = a * (y + k)
+        t = torch.where(xx < -0.5, 0.25 * torch.exp((xx + 0.5) / 0.5),
+                        torch.where(xx < 0.5, 0.5 * (1 + xx), 1 - 0.25 * torch.exp(-(xx - 0.5) / 0.5)))
+        t = torch.clamp(t, 0, 1)
+        return torch.where(t <= 0.0031308, 12.92 * t, 1.055 * torch.pow(torch.clamp(t, min=0.0031308), 1 / 2.4) - 0.055)
+
+    mse = ((tm(out) - tm(ref)) ** 2).mean(dim=(1, 2, 3))
+    return (10 * torch.log10(1.0 / mse)).mean().item()
+
+
+@torch.no_grad()
+def evaluate(cfg: FrameConfig, dnet, knet, seeds, frames=8, device="cuda", uniform=False,
+             budget=None, gen_seed=123):
+    """Mean tonemapped PSNR and relMSE over held-out clips, hard mask (test time)."""
+    if budget is not None:
+        cfg = dataclasses.replace(cfg, budget=budget)
+    cb = make_clips(seeds, cfg.H, cfg.W, frames, device, randomise_tmo=False)
+    gen = torch.Generator(device=device).manual_seed(gen_seed)
+    prev = None
+    ps, rm = [], []
+    for t in range(frames):
+        pool = sample_pool(cb.ref[t], gen)
+        mv = cb.mv[t] if prev is not None else None
+        out, _ = frame_forward(None if uniform else dnet, knet, cfg, cb.aux[t], prev, mv, pool,
+                               7_000_001 + t, t, "hard", uniform=uniform)
+        prev = out
+        ps.append(psnr_tonemapped(out, cb.ref[t], cb.params))
+        r = cb.ref[t][..., :3]
+        rm.append((((out[..., :3] - r) ** 2) / (r ** 2 + 1e-2)).mean().item())
+    return dict(psnr=float(np.mean(ps)), relmse=float(np.mean(rm)), budget=cfg.budget)

@@ -1,0 +1,97 @@
+"""End-to-end gradients of one frame (both networks) against the FP64 oracle, and a short
+training run on procedural clips."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import procgen
+from oracle import density as odens
+from oracle import features as ofeat
+from oracle import filt as ofilt
+from oracle import sampling as osamp
+from oracle import tmo as otmo
+from oracle import unet as ounet
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _small_cfg():
+    from paper_2602_08642_amd import pipeline
+    return dataclasses.replace(pipeline.CONFIGS["c4"], H=32, W=32, net_dtype=torch.float32,
+                               logit_dtype=torch.float32, widths=(8, 16, 16, 16))
+
+
+def test_frame_gradients_match_oracle():
+    from paper_2602_08642_amd import autograd as ag
+    from paper_2602_08642_amd import ops, pipeline, train
+    cfg = _small_cfg()
+    N, H, W = 2, cfg.H, cfg.W
+    dspec, kspec = pipeline.density_spec(cfg), pipeline.kernel_spec(cfg)
+    dw = procgen.init_weights(dspec, 3)
+    kw = procgen.init_weights(kspec, 4)
+    cb = train.make_clips([500, 501], H, W, 2, DEV)
+    gen = torch.Generator(device=DEV).manual_seed(0)
+    dnet = train.TrainNet(dspec, dw, torch.float32, DEV)
+    knet = train.TrainNet(kspec, kw, torch.float32, DEV)
+    prev = cb.ref[0].clone()                       # a history frame (constant input)
+    mv = cb.mv[1]
+    pool = train.sample_pool(cb.ref[1], gen)
+    seed, frame = 77, 1
+    out, s = train.frame_forward(dnet, knet, cfg, cb.aux[1], prev, mv, pool, seed, frame, "relaxed")
+    loss = ag.TMOLoss.apply(out, None, cb.ref[1], None, None, cb.params)
+    loss.backward()
+
+    # oracle: the same frame in FP64 with the GPU's s-derived mask and samples
+    cap = int(N * H * W * (cfg.budget + 1)) + 1024
+    req = ops.sample_mask(s.detach(), seed, frame, capacity=cap)
+    total = int(req["total"].item())
+    smp = ops.fixture_render(pool, req["count"], req["pixel_offset"], cap)[:total].cpu().numpy()
+    tw = lambda wd: {k: (torch.tensor(w, dtype=torch.float64, requires_grad=True),
+                         torch.tensor(b, dtype=torch.float64, requires_grad=True)) for k, (w, b) in wd.items()}
+    dwt, kwt = tw(dw), tw(kw)
+    aux = cb.aux[1].double().cpu()
+    p64, m64 = prev.double().cpu(), mv.double().cpu()
+    fs = ofeat.sampler_features(aux, p64, m64, cfg.sampler_cin)
+    z = odens.cnn_forward(fs, [(dwt[l["name"]][0], dwt[l["name"]][1], l["relu"]) for l in dspec])[..., 0]
+    s64 = odens.normalise(z, cfg.budget)
+    assert np.allclose(s64.detach().numpy(), s.detach().cpu().numpy(), rtol=1e-4)
+    L0 = osamp.scatter(s64, req["count"].cpu().numpy(), smp, seed, frame, "relaxed", 10.0)
+    Ls = osamp.pyramid(L0, cfg.levels)
+    fk = ofeat.kernel_features(aux, L0, s64, p64, m64, cfg.kernel_cin)
+    logits = ounet.unet_forward(fk, kwt, cfg.levels)
+    o64 = ofilt.denoise_pyramid(Ls, logits, cfg.KD, cfg.KU, cfg.KT, p64, m64)[0]
+    ltot = 0
+    for n in range(N):
+        prm = dict(zip(["k", "alpha", "beta", "s", "h"], cb.params[n].double().cpu().tolist()))
+        ltot = ltot + otmo.frame_loss(otmo.tonemap(o64[n:n + 1], prm),
+                                      otmo.tonemap(cb.ref[1][n:n + 1].double().cpu(), prm)) / N
+    ltot.backward()
+    assert abs(float(loss.item()) - float(ltot)) < 1e-4 * abs(float(ltot))
+    worst = 0.0
+    for net, ref in ((knet, kwt), (dnet, dwt)):
+        for name, lr in net.layers.items():
+            wscale = float(ref[name][0].grad.norm())
+            for g, r in ((lr.w.grad, ref[name][0].grad), (lr.b.grad, ref[name][1].grad)):
+                gn, rn = g.double().cpu(), r
+                # floor: a gradient that vanishes exactly is compared on its layer's scale
+                rel = float((gn - rn).norm() / max(float(rn.norm()), 1e-3 * wscale, 1e-30))
+                worst = max(worst, rel)
+                assert rel < 2e-3, (name, rel)
+    # the budget softmax is shift invariant: the sampler's output bias gets no gradient
+    assert float(dwt["d2"][1].grad.abs().max()) < 1e-10
+    assert float(dnet.layers["d2"].b.grad.abs().max()) < 1e-4 * float(dwt["d2"][0].grad.norm())
+    print(f"worst normwise parameter-gradient error {worst:.2e}")
+
+
+def test_training_reduces_loss():
+    from paper_2602_08642_amd import pipeline, train
+    cfg = dataclasses.replace(pipeline.CONFIGS["c4"], H=64, W=64)
+    tc = train.TrainConfig(steps=40, batch=2, frames=3, lr=2e-3, n_train_clips=4, log_every=100)
+    _, _, hist = train.train(cfg, tc, DEV, log=lambda *a: None)
+    first = np.mean([h["loss"] for h in hist[:8]])
+    last = np.mean([h["loss"] for h in hist[-8:]])
+    assert all(np.isfinite(h["loss"]) for h in hist)
+    assert last < first, (first, last)

@@ -152,3 +152,39 @@ def test_tmo_loss_gradient_fd():
     prm = dict(k=0.1, alpha=0.4, beta=1.1, s=0.4, h=0.6)
     f = lambda t: tmo.frame_loss(tmo.tonemap(t, prm), tmo.tonemap(ref, prm))
     assert torch.autograd.gradcheck(f, (L,), eps=1e-7, atol=1e-6)
+
+
+def test_adamw_matches_torch_optimizer():
+    from oracle import optim
+    rng = np.random.default_rng(0)
+    p0 = rng.normal(size=50)
+    tp = torch.tensor(p0.copy(), requires_grad=True)
+    opt = torch.optim.AdamW([tp], lr=1e-2, betas=(0.8, 0.985), eps=1e-8, weight_decay=0.02)
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for t in range(1, 6):
+        g = rng.normal(size=50)
+        tp.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = optim.adamw_step(p, g, m, v, t, 1e-2)
+        assert np.allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_feature_pins():
+    from oracle import features as of
+    v = torch.tensor([-3.0, -0.5, 0.0, 0.25, 10.0], dtype=torch.float64)
+    assert torch.allclose(of.slog1p(v), torch.tensor(np.sign(v.numpy()) * np.log1p(np.abs(v.numpy()))))
+    L = torch.rand(1, 3, 4, 4, dtype=torch.float64) * 5
+    prm = dict(k=0.0, alpha=0.4, beta=1.0, s=0.5, h=0.5)
+    assert torch.allclose(of.tonemap_eval(L[..., :3]), tmo.tonemap(L, prm), rtol=1e-14)
+    aux = torch.rand(1, 3, 4, 8, dtype=torch.float64)
+    L0 = torch.randn(1, 3, 4, 4, dtype=torch.float64)
+    s = torch.rand(1, 3, 4, dtype=torch.float64)
+    f = of.kernel_features(aux, L0, s)
+    assert f.shape == (1, 3, 4, 16)
+    assert torch.equal(f[..., :7], aux[..., :7]) and torch.equal(f[..., 10], s)
+    assert torch.all(f[..., 11:] == 0)
+    mv = torch.zeros(1, 3, 4, 2, dtype=torch.float64)
+    mv[0, 0, 0] = torch.tensor([-0.6, 0.0])     # leaves the frame at the left edge
+    f2 = of.kernel_features(aux, L0, s, L0, mv)
+    assert f2[0, 0, 0, 14] == 0 and f2[0, 1, 1, 14] == 1
+    assert torch.allclose(f2[0, 1, 1, 11:14], of.slog1p(L0[0, 1, 1, :3]))
