@@ -101,29 +101,14 @@ def cpu_baseline(cfg, dw, kw, rows: int):
                        f"normalisation, mask, scatter, pyramid, U-Net, gathering pyramid) in FP64")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2")
-    ap.add_argument("--cpu-rows", type=int, default=64)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding of a "
-                                   "frame is designed (see DESIGN.md) but not built"}))
-        sys.exit(2)
-
+def bench_config(name, steps, warmup, dev, seed=2602):
+    """Time one frame configuration; returns the per-config result dict."""
     import torch
 
     import procgen
     from paper_2602_08642_amd import ops, pipeline
 
-    cfg = pipeline.CONFIGS[args.config]
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    seed = 2602
+    cfg = pipeline.CONFIGS[name]
     dspec, kspec = pipeline.density_spec(cfg), pipeline.kernel_spec(cfg)
     dw = procgen.init_weights(dspec, 7)
     kw = procgen.init_weights(kspec, 8)
@@ -139,23 +124,19 @@ def main():
         pt = torch.zeros((1, cfg.H, cfg.W, 4), dtype=torch.float32)
         pt[0, ..., :3] = torch.tensor(f0.truth)
         prev = pt.to(dev)
-
+    del fr, sc
     learned = pipeline.FrameRenderer(cfg, dw, kw, dev)
     uniform = pipeline.FrameRenderer(cfg, None, None, dev, uniform=True)
-
-    def render(r, req):
-        return ops.fixture_render(pool, req["count"], req["pixel_offset"], req["capacity"])
-
     frame = 1
     # pre-render the (deterministic) sample requests of both paths
     s_l = learned.density(aux, prev, mv)
     req_l = learned.request(s_l, seed, frame)
-    smp_l = render(learned, req_l)
+    smp_l = ops.fixture_render(pool, req_l["count"], req_l["pixel_offset"], req_l["capacity"])
     s_u = uniform.density(aux)
     req_u = uniform.request(s_u, seed, frame)
-    smp_u = render(uniform, req_u)
+    smp_u = ops.fixture_render(pool, req_u["count"], req_u["pixel_offset"], req_u["capacity"])
+    del pool
     torch.cuda.synchronize()
-
     stream = torch.cuda.current_stream()
 
     def run(r, smp, events=None):
@@ -183,23 +164,23 @@ def main():
         return out
 
     def timed(r, smp):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             run(r, smp)
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
         t0 = time.perf_counter()
-        for k in range(args.steps):
+        for k in range(steps):
             run(r, smp, evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        stages = [[evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)] for i in range(6)]
-        frame_ms = [evs[k][0].elapsed_time(evs[k][6]) for k in range(args.steps)]
+        stages = [[evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)] for i in range(6)]
+        frame_ms = [evs[k][0].elapsed_time(evs[k][6]) for k in range(steps)]
         return wall, frame_ms, stages
 
     wall_l, fms_l, st_l = timed(learned, smp_l)
     wall_u, fms_u, st_u = timed(uniform, smp_u)
     mean = lambda v: sum(v) / len(v)
-    ms = wall_l * 1e3 / args.steps
+    ms = wall_l * 1e3 / steps
     names = ["density", "mask", "scatter_pyramid", "features", "unet", "filter"]
     flops = unet_flops(cfg, kspec)
     unet_ms = mean(st_l[4])
@@ -208,43 +189,134 @@ def main():
     fp32 = cfg.net_dtype == torch.float32
     peak = PEAK["fp32_mfma_TFLOPs"] if fp32 else PEAK["bf16_mfma_TFLOPs"]
     achieved = flops / (unet_ms * 1e-3) / 1e12
+    fgbs = fbytes / (filt_ms * 1e-3) / 1e9
+    return dict(
+        cfg=cfg, dw=dw, kw=kw, ms=ms, fps=1e3 / ms, mpx=cfg.H * cfg.W / (ms * 1e3),
+        event_ms=mean(fms_l), stages={n: round(mean(v), 4) for n, v in zip(names, st_l)},
+        uniform={"ms_per_frame": round(wall_u * 1e3 / steps, 4),
+                 "Mpixel_per_s": round(cfg.H * cfg.W / (wall_u * 1e6 / steps), 3),
+                 "stages_ms": {n: round(mean(v), 4) for n, v in zip(names, st_u)},
+                 "what": "s = B everywhere, all-zero logits (box-weighted pyramid)"},
+        roofline={"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                  "frac": round(achieved / peak, 4), "traffic": None,
+                  "kernel": "k_conv (implicit-GEMM MFMA conv), all U-Net launches of one frame",
+                  "algorithmic_flop_per_frame": flops},
+        filter_roofline={"bound": "hbm", "achieved": round(fgbs, 1), "peak": PEAK["hbm_GBps"],
+                         "unit": "GB/s", "frac": round(fgbs / PEAK["hbm_GBps"], 4),
+                         "algorithmic_bytes_per_frame": fbytes},
+        workload=(f"{cfg.name}: {cfg.W}x{cfg.H} frame, {cfg.budget} spp, {cfg.levels}-level kd "
+                  f"{cfg.KD}x{cfg.KD} / ku {cfg.KU}x{cfg.KU}"
+                  + (f" / kt {cfg.KT}x{cfg.KT}" if cfg.temporal else "")
+                  + f", U-Net 32-64-128-256 ({'fp32' if fp32 else 'bf16'} MFMA)"))
+
+
+WEIGHTS = os.path.join(ROOT, "paper_2602_08642_amd", "weights", "c4_trained.npz")
+
+
+def quality(dev, seeds=(10000, 10001, 10002, 10003), frames=8):
+    """Learned vs uniform vs fallback error on held-out procedural clips with the trained
+    weights (256x256, 0.25 spp), and the uniform budget that matches the learned error."""
+    from paper_2602_08642_amd import evaluate, pipeline, train
+    if not os.path.exists(WEIGHTS):
+        return None
+    w = evaluate.load_weights(WEIGHTS)
+    cfg = pipeline.CONFIGS["c4"]
+    dnet = train.TrainNet(pipeline.density_spec(cfg), w["density"], cfg.net_dtype, dev)
+    kl = train.TrainNet(pipeline.kernel_spec(cfg), w["kernel_learned"], cfg.net_dtype, dev)
+    ku = train.TrainNet(pipeline.kernel_spec(cfg), w["kernel_uniform"], cfg.net_dtype, dev)
+    seeds = list(seeds)
+    res = {"workload": "held-out procedural 256x256 clips x 8 frames, 0.25 spp, hard mask",
+           "learned": train.evaluate(cfg, dnet, kl, seeds, frames, dev),
+           "uniform": train.evaluate(cfg, None, ku, seeds, frames, dev, uniform=True),
+           "fallback": train.evaluate(cfg, None, None, seeds, frames, dev, uniform=True)}
+    sweep = [train.evaluate(cfg, None, ku, seeds, frames, dev, uniform=True, budget=b)
+             for b in (0.25, 0.3, 0.35, 0.4, 0.5, 0.6, 0.75, 1.0)]
+    tgt = res["learned"]["psnr"]
+    eq = None
+    for a, b in zip(sweep[:-1], sweep[1:]):
+        if a["psnr"] <= tgt <= b["psnr"] and b["psnr"] > a["psnr"]:
+            eq = a["budget"] + (tgt - a["psnr"]) / (b["psnr"] - a["psnr"]) * (b["budget"] - a["budget"])
+            break
+    res["uniform_budget_sweep_psnr"] = {str(s["budget"]): round(s["psnr"], 3) for s in sweep}
+    res["equal_error_uniform_spp"] = None if eq is None else round(eq, 4)
+    res["equal_error_sample_ratio"] = None if eq is None else round(eq / cfg.budget, 3)
+    res["psnr_gain_db_vs_uniform"] = round(res["learned"]["psnr"] - res["uniform"]["psnr"], 3)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--also", default="c3,c5", help="other configurations timed beside (or '')")
+    ap.add_argument("--cpu-rows", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (scales the HBM "
+                         "traffic counters FETCH_SIZE / WRITE_SIZE of a profiled run)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 3}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding of a "
+                                   "frame is designed (see DESIGN.md) but not built"}))
+        sys.exit(2)
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    r = bench_config(args.config, args.steps, args.warmup, dev)
+    cfg = r["cfg"]
     res = {
         "metric": "ms/frame & Mpixel/s at 1080p 0.25spp, learned vs uniform sampling at equal error",
-        "value": round(cfg.H * cfg.W / (ms * 1e3), 3),
+        "value": round(r["mpx"], 3),
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": round(r["ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if fp32 else "bf16",
+        "dtype": "f32" if cfg.net_dtype == torch.float32 else "bf16",
         "data": "synthetic (procedural blobs+polygons scene, seeded random-init weights)",
-        "config": {"workload": f"{cfg.name}: {cfg.W}x{cfg.H} frame, {cfg.budget} spp, "
-                               f"{cfg.levels}-level kd {cfg.KD}x{cfg.KD} / ku {cfg.KU}x{cfg.KU}"
-                               + (f" / kt {cfg.KT}x{cfg.KT}" if cfg.temporal else "")
-                               + f", U-Net 32-64-128-256 ({'fp32' if fp32 else 'bf16'} MFMA)",
-                   "global_batch": 1, "frames_per_step": 1},
-        "frames_per_s": round(1e3 / ms, 2),
-        "ms_per_frame_event_mean": round(mean(fms_l), 4),
-        "stages_ms": {n: round(mean(v), 4) for n, v in zip(names, st_l)},
-        "uniform_fallback": {
-            "ms_per_frame": round(wall_u * 1e3 / args.steps, 4),
-            "Mpixel_per_s": round(cfg.H * cfg.W / (wall_u * 1e6 / args.steps), 3),
-            "stages_ms": {n: round(mean(v), 4) for n, v in zip(names, st_u)},
-            "what": "s = B everywhere, all-zero logits (box-weighted pyramid)"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "k_conv (implicit-GEMM MFMA conv), all U-Net launches of one frame",
-                     "algorithmic_flop_per_frame": flops},
-        "filter_roofline": {"bound": "hbm", "achieved": round(fbytes / (filt_ms * 1e-3) / 1e9, 1),
-                            "peak": PEAK["hbm_GBps"], "unit": "GB/s",
-                            "frac": round(fbytes / (filt_ms * 1e-3) / 1e9 / PEAK["hbm_GBps"], 4),
-                            "algorithmic_bytes_per_frame": fbytes},
+        "config": {"workload": r["workload"], "global_batch": 1, "frames_per_step": 1},
+        "frames_per_s": round(r["fps"], 2),
+        "ms_per_frame_event_mean": round(r["event_ms"], 4),
+        "stages_ms": r["stages"],
+        "uniform_fallback": r["uniform"],
+        "roofline": r["roofline"],
+        "filter_roofline": r["filter_roofline"],
     }
+    also = {}
+    for name in [a for a in args.also.split(",") if a and a != args.config]:
+        o = bench_config(name, max(3, args.steps // 2), max(1, args.warmup // 2), dev)
+        also[name] = {"workload": o["workload"], "ms_per_frame": round(o["ms"], 4),
+                      "frames_per_s": round(o["fps"], 2), "Mpixel_per_s": round(o["mpx"], 3),
+                      "stages_ms": o["stages"], "uniform_fallback": o["uniform"],
+                      "roofline": o["roofline"], "filter_roofline": o["filter_roofline"]}
+        del o
+        torch.cuda.empty_cache()
+    if also:
+        res["also_timed"] = also
+    if not args.no_quality:
+        q = quality(dev)
+        if q is not None:
+            res["learned_vs_uniform"] = q
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(cfg, dw, kw, args.cpu_rows)
+        res["cpu_baseline"] = cpu_baseline(cfg, r["dw"], r["kw"], args.cpu_rows)
     print(json.dumps(res))
 
 

@@ -91,6 +91,16 @@ int aps_conv2d_fwd(const void* x, const void* x2, int N, int H, int W, int Cx, i
                    const void* packed_w, const float* bias, int Cout, int ksize, int relu,
                    int dtype, void* y, int ldy, int y_dtype, void* stream);
 
+/* A 3x3 conv (Cout 32 or 64, input as aps_conv2d_fwd, Cx + C2 > 16) with a 1x1 head
+ * (K <= 64 outputs, packed_head from aps_conv_pack_weights(.., K, 1, Cout, ..)) applied to its
+ * output in the same kernel: logits [N,H,W,kstride] = head(y).  y (nullable) receives the
+ * conv output itself [N,H,W,ldy]; when NULL it is not written.  Inputs, y and logits share
+ * dtype.  The logits equal those of the two separate calls bit for bit. */
+int aps_conv2d_fwd_head(const void* x, const void* x2, int N, int H, int W, int Cx, int C2,
+                        int mode, const void* packed_w, const float* bias, int Cout, int relu,
+                        const void* packed_head, const float* head_bias, int K, int dtype,
+                        void* y, int ldy, void* logits, int kstride, void* stream);
+
 /* ---------------------------------------------------------------- a1 + a2: density
  * Sec. 3 (Overview): the sampler predicts one channel z; s = f*B + (1-f)*B*Npx*softmax(z)
  * with the softmax over the H*W pixels of each frame, so sum(s) = Npx*B and s >= f*B
@@ -148,7 +158,7 @@ int aps_scatter_samples(const float* s, const uint8_t* count, const int32_t* pix
 /* Network inputs (C <= 16 channels, zero padded), out [N,H,W,C] in out_dtype.
  *   APS_FEAT_SAMPLER: aux[0..6], then with prev: tonemap(W prev) RGB, valid
  *   APS_FEAT_KERNEL : aux[0..6], slog1p(L0) RGB, s, then with prev: slog1p(W prev) RGB, valid
- * aux float32 [N,H,W,8] (albedo 3, normal 3, log-depth 1, pad); W prev = bilinear warp of the
+ * aux float32 [N,H,W,8] (albedo 3, normal 3, log-depth 1, pad); C is 8 or 16; W prev = bilinear warp of the
  * previous output along mv (see aps_reproject); valid = the back-projected position lies in
  * the frame; slog1p(v) = sign(v) log(1+|v|); tonemap = the evaluation filmic curve of Sec. 5
  * (s = h = 0.5, contrast 0.4, exposure 0, saturation 1) followed by the sRGB transfer. */

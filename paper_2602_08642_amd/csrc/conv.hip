@@ -27,6 +27,12 @@ struct ConvArgs {
   int Cout, nchunk, ntx;
   void* y;
   int ldy, relu;
+  // optional 1x1 head fused into the epilogue (see k_conv); store_main = also write y
+  const void* hw;
+  const float* hb;
+  int hK;
+  void* hy;
+  int hldy, store_main;
 };
 
 // ---- 8-element vectors of the storage type ---------------------------------------------
@@ -172,7 +178,11 @@ __device__ inline void store_out<uint16_t>(uint16_t* p, int ldy, int co0, int Co
   }
 }
 
-template <typename T, typename TO, int KS, int TM, int TN>
+// CG = 8-channel input groups per pixel in the K layout.  CG = 4: K walks 32-channel chunks,
+// one tap per MFMA step.  CG = 1 or 2 (inputs of at most 8 or 16 channels, a single chunk): K
+// enumerates (tap, group) pairs, so one MFMA step covers 4 / CG taps and no MFMA work is
+// spent on channel padding; lane group q of step s takes pair p = 4 s + q.
+template <typename T, typename TO, int KS, int TM, int TN, int CG, bool HEAD = false>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   constexpr int R = KS / 2;
   constexpr int TH = 4 * TN, TWp = 16;
@@ -191,7 +201,35 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int c = 0; c < a.nchunk; ++c) {
+  if constexpr (CG < 4) {
+    constexpr int NPAIR = KS * KS * CG, STEPS = (NPAIR + 3) / 4;
+    for (int it = tid; it < SH * SW * CG; it += 256) {
+      const int g = it % CG, p = it / CG;
+      const int r = p / SW, col = p % SW;
+      stage8<T>(a, n, ty0 - R + r, tx0 - R + col, g * 8, Xs + p * PS + g * 8);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+      const int p = 4 * s + (lane >> 4);
+      const int tap = p < NPAIR ? p / CG : 0, g = p < NPAIR ? p % CG : 0;  // padded pairs: zero weights
+      const int dy = tap / KS - R, dx = tap % KS - R;
+      Frag<T> wf[TM];
+#pragma unroll
+      for (int m = 0; m < TM; ++m)
+        frag_load(wf[m], wp + ((((size_t)(cob * TM + m) * STEPS + s) * 64 + lane) * 8));
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int row = wave * TN + j + R + dy, col = (lane & 15) + R + dx;
+        Frag<T> bf;
+        frag_load(bf, Xs + (row * SW + col) * PS + g * 8);
+#pragma unroll
+        for (int m = 0; m < TM; ++m) acc[m][j] = mma(wf[m], bf, acc[m][j]);
+      }
+    }
+  }
+
+  for (int c = 0; c < (CG < 4 ? 0 : a.nchunk); ++c) {
     for (int it = tid; it < SH * SW * 4; it += 256) {
       const int g = it & 3, p = it >> 2;
       const int r = p / SW, col = p % SW;
@@ -220,22 +258,74 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   }
 
   TO* y = static_cast<TO*>(a.y);
+  if constexpr (!HEAD) {
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int row = ty0 + wave * TN + j, col = tx0 + (lane & 15);
-    if (row >= a.H || col >= a.W) continue;
-    TO* py = y + (((size_t)n * a.H + row) * a.W + col) * a.ldy;
+    for (int j = 0; j < TN; ++j) {
+      const int row = ty0 + wave * TN + j, col = tx0 + (lane & 15);
+      if (row >= a.H || col >= a.W) continue;
+      TO* py = y + (((size_t)n * a.H + row) * a.W + col) * a.ldy;
 #pragma unroll
-    for (int m = 0; m < TM; ++m) {
-      const int co0 = (cob * TM + m) * 16 + 4 * (lane >> 4);
-      if (co0 >= a.Cout) continue;
-      float v[4];
+      for (int m = 0; m < TM; ++m) {
+        const int co0 = (cob * TM + m) * 16 + 4 * (lane >> 4);
+        if (co0 >= a.Cout) continue;
+        float v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float t = acc[m][j][q] + (co0 + q < a.Cout && a.bias ? a.bias[co0 + q] : 0.f);
-        v[q] = a.relu ? fmaxf(t, 0.f) : t;
+        for (int q = 0; q < 4; ++q) {
+          float t = acc[m][j][q] + (co0 + q < a.Cout && a.bias ? a.bias[co0 + q] : 0.f);
+          v[q] = a.relu ? fmaxf(t, 0.f) : t;
+        }
+        store_out<TO>(py, a.ldy, co0, a.Cout, v);
       }
-      store_out<TO>(py, a.ldy, co0, a.Cout, v);
+    }
+  } else {
+    // Fused 1x1 head on this layer's output (all Cout = 16 TM channels are in this block):
+    // each wave re-lays its row-j tile [16 px][16 TM ch] out through LDS as MFMA B fragments
+    // and multiplies it by the packed head weights, the same operands in the same order as
+    // the stand-alone 1x1 convolution of the stored tile.
+    constexpr int CC = TM * 16, YP = CC + (sizeof(T) == 2 ? 8 : 4);
+    T* Ys = Xs + wave * 16 * YP;
+    const T* hw = static_cast<const T*>(a.hw);
+    TO* hy = static_cast<TO*>(a.hy);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int row = ty0 + wave * TN + j, col = tx0 + (lane & 15);
+      const bool inpx = row < a.H && col < a.W;
+#pragma unroll
+      for (int m = 0; m < TM; ++m) {
+        const int co0 = m * 16 + 4 * (lane >> 4);
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float t = acc[m][j][q] + (a.bias ? a.bias[co0 + q] : 0.f);
+          v[q] = a.relu ? fmaxf(t, 0.f) : t;
+          Ys[(lane & 15) * YP + co0 + q] = f2t<T>(v[q]);
+        }
+        if (a.store_main && inpx)
+          store_out<TO>(y + (((size_t)n * a.H + row) * a.W + col) * a.ldy, a.ldy, co0, a.Cout, v);
+      }
+      __syncthreads();
+      Frag<T> bf[TM / 2];
+#pragma unroll
+      for (int cc = 0; cc < TM / 2; ++cc) frag_load(bf[cc], Ys + (lane & 15) * YP + 32 * cc + 8 * (lane >> 4));
+#pragma unroll
+      for (int mh = 0; mh < 4; ++mh) {
+        if (mh * 16 >= a.hK) break;
+        f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int cc = 0; cc < TM / 2; ++cc) {
+          Frag<T> wf;
+          frag_load(wf, hw + ((((size_t)mh * (TM / 2)) + cc) * 64 + lane) * 8);
+          h = mma(wf, bf[cc], h);
+        }
+        const int k0 = mh * 16 + 4 * (lane >> 4);
+        if (inpx && k0 < a.hK) {
+          float v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = h[q] + (k0 + q < a.hK ? a.hb[k0 + q] : 0.f);
+          store_out<TO>(hy + (((size_t)n * a.H + row) * a.W + col) * a.hldy, a.hldy, k0, a.hK, v);
+        }
+      }
+      __syncthreads();
     }
   }
 }
@@ -247,31 +337,53 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 //     w'[co'][tap][ci'] = w[ci'][KS*KS - 1 - tap][co']   (channels swapped, taps flipped).
 template <typename T>
 __global__ void k_pack(const float* __restrict__ w, int Cout, int KS, int Cin, int nchunk,
-                       size_t total, T* __restrict__ out, int transpose) {
+                       size_t total, T* __restrict__ out, int transpose, int cg) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= total) return;
   const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
   size_t r = i >> 9;
-  const int c = (int)(r % nchunk);
-  r /= nchunk;
-  const int tap = (int)(r % (KS * KS));
-  const int ct = (int)(r / (KS * KS));
-  const int co = ct * 16 + (lane & 15), ci = c * kChunk + (lane >> 4) * 8 + e;
+  int ct, tap, ci;
+  bool ok = true;
+  if (cg < 4) {  // merged (tap, group) pairs: step s, lane group q -> pair 4 s + q
+    const int npair = KS * KS * cg, steps = (npair + 3) / 4;
+    const int st = (int)(r % steps);
+    ct = (int)(r / steps);
+    const int p = 4 * st + (lane >> 4);
+    ok = p < npair;
+    tap = ok ? p / cg : 0;
+    ci = (ok ? p % cg : 0) * 8 + e;
+  } else {
+    const int c = (int)(r % nchunk);
+    r /= nchunk;
+    tap = (int)(r % (KS * KS));
+    ct = (int)(r / (KS * KS));
+    ci = c * kChunk + (lane >> 4) * 8 + e;
+  }
+  const int co = ct * 16 + (lane & 15);
   float v = 0.f;
-  if (co < Cout && ci < Cin)
+  if (ok && co < Cout && ci < Cin)
     v = transpose ? w[((size_t)ci * KS * KS + (KS * KS - 1 - tap)) * Cout + co]
                   : w[((size_t)co * KS * KS + tap) * Cin + ci];
   if constexpr (sizeof(T) == 2) out[i] = f2bf(v);
   else out[i] = v;
 }
 
+// 8-channel groups of the K layout (see k_conv): merged taps only for 3x3 with <= 16 channels
+int conv_cg(int KS, int Cin) {
+  if (KS != 3) return 4;
+  const int g = (Cin + 7) / 8;
+  return g <= 1 ? 1 : (g <= 2 ? 2 : 4);
+}
+
 size_t packed_elems(int Cout, int KS, int Cin) {
   const size_t nct = (size_t)((Cout + 16 * kMaxTM - 1) / (16 * kMaxTM)) * kMaxTM;
+  const int cg = conv_cg(KS, Cin);
+  if (cg < 4) return nct * ((KS * KS * cg + 3) / 4) * 512;
   const size_t nchunk = (size_t)(Cin + kChunk - 1) / kChunk;
   return nct * KS * KS * nchunk * 512;
 }
 
-template <typename T, typename TO, int KS, int TM, int TN>
+template <typename T, typename TO, int KS, int TM, int TN, int CG>
 void launch_conv(const ConvArgs& a, hipStream_t st) {
   const int TH = 4 * TN;
   const int ntx = (a.W + 15) / 16, nty = (a.H + TH - 1) / TH;
@@ -279,25 +391,43 @@ void launch_conv(const ConvArgs& a, hipStream_t st) {
   b.ntx = ntx;
   const int nco = (a.Cout + 16 * TM - 1) / (16 * TM);
   dim3 grid(ntx * nty, nco, a.N);
-  k_conv<T, TO, KS, TM, TN><<<grid, 256, 0, st>>>(b);
+  k_conv<T, TO, KS, TM, TN, CG><<<grid, 256, 0, st>>>(b);
 }
 
-template <typename T, typename TO, int KS>
+// 3x3 conv (Cout = 16 TM, one block covers all of it) with its 1x1 head in the epilogue.
+template <typename T, int TM>
+void launch_conv_head(const ConvArgs& a, hipStream_t st) {
+  const bool big = (size_t)a.H * a.W >= 64 * 64;
+  const int TN = big ? 4 : 2, TH = 4 * TN;
+  ConvArgs b = a;
+  b.ntx = (a.W + 15) / 16;
+  dim3 grid(b.ntx * ((a.H + TH - 1) / TH), 1, a.N);
+  if (big) k_conv<T, T, 3, TM, 4, 4, true><<<grid, 256, 0, st>>>(b);
+  else k_conv<T, T, 3, TM, 2, 4, true><<<grid, 256, 0, st>>>(b);
+}
+
+template <typename T, typename TO, int KS, int CG>
 void dispatch_tiles(const ConvArgs& a, hipStream_t st) {
   const bool big = (size_t)a.H * a.W >= 64 * 64;
   if (a.Cout <= 16) {
-    if (big) launch_conv<T, TO, KS, 1, 4>(a, st); else launch_conv<T, TO, KS, 1, 2>(a, st);
+    if (big) launch_conv<T, TO, KS, 1, 4, CG>(a, st); else launch_conv<T, TO, KS, 1, 2, CG>(a, st);
   } else if (a.Cout <= 32) {
-    if (big) launch_conv<T, TO, KS, 2, 4>(a, st); else launch_conv<T, TO, KS, 2, 2>(a, st);
+    if (big) launch_conv<T, TO, KS, 2, 4, CG>(a, st); else launch_conv<T, TO, KS, 2, 2, CG>(a, st);
   } else {
-    if (big) launch_conv<T, TO, KS, 4, 4>(a, st); else launch_conv<T, TO, KS, 4, 2>(a, st);
+    if (big) launch_conv<T, TO, KS, 4, 4, CG>(a, st); else launch_conv<T, TO, KS, 4, 2, CG>(a, st);
   }
 }
 
 template <typename T, typename TO>
 void dispatch_ks(const ConvArgs& a, int KS, hipStream_t st) {
-  if (KS == 3) dispatch_tiles<T, TO, 3>(a, st);
-  else dispatch_tiles<T, TO, 1>(a, st);
+  if (KS == 3) {
+    const int cg = conv_cg(3, a.Cx + a.C2);
+    if (cg == 1) dispatch_tiles<T, TO, 3, 1>(a, st);
+    else if (cg == 2) dispatch_tiles<T, TO, 3, 2>(a, st);
+    else dispatch_tiles<T, TO, 3, 4>(a, st);
+  } else {
+    dispatch_tiles<T, TO, 1, 4>(a, st);
+  }
 }
 
 // ======================================================================== backward
@@ -552,10 +682,11 @@ static int pack_impl(const float* w, int Cout, int ksize, int Cin, int dtype, vo
   hipStream_t st = as_stream(stream);
   if (dtype == APS_F32)
     k_pack<float><<<blocks, 256, 0, st>>>(w, co, ksize, ci, nchunk, total,
-                                          static_cast<float*>(packed), transpose);
+                                          static_cast<float*>(packed), transpose, conv_cg(ksize, ci));
   else if (dtype == APS_BF16)
     k_pack<uint16_t><<<blocks, 256, 0, st>>>(w, co, ksize, ci, nchunk, total,
-                                             static_cast<uint16_t*>(packed), transpose);
+                                             static_cast<uint16_t*>(packed), transpose,
+                                             conv_cg(ksize, ci));
   else
     return APS_ERR_UNSUPPORTED;
   APS_LAUNCH_CHECK();
@@ -643,7 +774,9 @@ int aps_conv2d_bwd_data(const void* dy, const void* ymask, int ldy, int N, int H
   a.bias = nullptr;
   a.Cout = Cin;
   a.nchunk = (ldy + kChunk - 1) / kChunk;
-  if (a.nchunk != (Cout + kChunk - 1) / kChunk) return APS_ERR_SHAPE;
+  // the operator was packed for Cout input channels: the padded stride must give the same layout
+  if (a.nchunk != (Cout + kChunk - 1) / kChunk || conv_cg(ksize, ldy) != conv_cg(ksize, Cout))
+    return APS_ERR_SHAPE;
   a.y = dX;
   a.ldy = Cin;
   a.relu = 0;
@@ -766,6 +899,62 @@ int aps_conv2d_bwd_weight(const void* x, const void* x2, int mode, int N, int H,
           static_cast<const uint16_t*>(dy), static_cast<const uint16_t*>(ymask), ldy, Cout, npix,
           p.bias_per, bpart);
     k_bias_reduce<<<(Cout + 255) / 256, 256, 0, st>>>(bpart, (int)p.bias_blocks, Cout, db);
+  }
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int aps_conv2d_fwd_head(const void* x, const void* x2, int N, int H, int W, int Cx, int C2,
+                        int mode, const void* packed_w, const float* bias, int Cout, int relu,
+                        const void* packed_head, const float* head_bias, int K, int dtype,
+                        void* y, int ldy, void* logits, int kstride, void* stream) {
+  if (N < 0 || H < 0 || W < 0 || Cx <= 0 || C2 < 0 || K <= 0 || kstride < K) return APS_ERR_SHAPE;
+  if (Cout != 32 && Cout != 64) return APS_ERR_UNSUPPORTED;
+  if (K > 64 || Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2) != 4) return APS_ERR_UNSUPPORTED;
+  if (y && ldy < Cout) return APS_ERR_SHAPE;
+  if (mode == APS_CONV_UP2_CAT) {
+    if (!x2 || C2 <= 0) return APS_ERR_NULL;
+    if (H % 2 || W % 2) return APS_ERR_SHAPE;
+  } else if (mode == APS_CONV_DIRECT || mode == APS_CONV_POOL2) {
+    if (C2 != 0) return APS_ERR_SHAPE;
+  } else {
+    return APS_ERR_ARG;
+  }
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!x || !packed_w || !bias || !packed_head || !head_bias || !logits) return APS_ERR_NULL;
+  ConvArgs a{};
+  a.x = x;
+  a.x2 = x2;
+  a.N = N;
+  a.H = H;
+  a.W = W;
+  a.Cx = Cx;
+  a.C2 = C2;
+  a.mode = mode;
+  a.wp = packed_w;
+  a.bias = bias;
+  a.Cout = Cout;
+  a.nchunk = (Cx + C2 + kChunk - 1) / kChunk;
+  a.y = y;
+  a.ldy = y ? ldy : Cout;
+  a.relu = relu;
+  a.hw = packed_head;
+  a.hb = head_bias;
+  a.hK = K;
+  a.hy = logits;
+  a.hldy = kstride;
+  a.store_main = y != nullptr;
+  hipStream_t st = as_stream(stream);
+  if (dtype == APS_F32) {
+    if (Cout == 32) launch_conv_head<float, 2>(a, st); else launch_conv_head<float, 4>(a, st);
+  } else if (dtype == APS_BF16) {
+    if (Cout == 32) launch_conv_head<uint16_t, 2>(a, st); else launch_conv_head<uint16_t, 4>(a, st);
+  } else {
+    return APS_ERR_UNSUPPORTED;
   }
   APS_LAUNCH_CHECK();
   return APS_OK;

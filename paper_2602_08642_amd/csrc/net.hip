@@ -131,14 +131,46 @@ int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W
   APS_TRY(conv(L[8], e3, e2, N, H2, W2, c3, c2, APS_CONV_UP2_CAT, dt, t, L[8].cout, dt, stream));
   APS_TRY(conv(L[9], t, nullptr, N, H2, W2, L[8].cout, 0, APS_CONV_DIRECT, dt, d2, c2, dt, stream));
   APS_TRY(conv(L[10], d2, e1, N, H1, W1, c2, c1, APS_CONV_UP2_CAT, dt, t, L[10].cout, dt, stream));
-  APS_TRY(conv(L[11], t, nullptr, N, H1, W1, L[10].cout, 0, APS_CONV_DIRECT, dt, d1, c1, dt, stream));
+  // dec1b with head1 fused into its epilogue (d1 is stored too: dec0a reads it)
+  bool fused1 = false;
+  if (n_heads > 1 && logit_dtype == dt && logits && logits[1] && kstride) {
+    const aps_conv_layer& A = L[11];
+    const aps_conv_layer& Hd = L[kUnetConvs + 1];
+    if (A.w && A.b && Hd.w && Hd.b && A.cin == L[10].cout && Hd.cin == A.cout && Hd.ksize == 1 &&
+        A.ksize == 3) {
+      const int r = aps_conv2d_fwd_head(t, nullptr, N, H1, W1, L[10].cout, 0, APS_CONV_DIRECT, A.w,
+                                        A.b, A.cout, A.relu, Hd.w, Hd.b, Hd.cout, dt, d1, c1,
+                                        logits[1], kstride[1], stream);
+      if (r == APS_OK) fused1 = true;
+      else if (r != APS_ERR_UNSUPPORTED) return r;
+    }
+  }
+  if (!fused1)
+    APS_TRY(conv(L[11], t, nullptr, N, H1, W1, L[10].cout, 0, APS_CONV_DIRECT, dt, d1, c1, dt, stream));
   APS_TRY(conv(L[12], d1, e0, N, H, W, c1, c0, APS_CONV_UP2_CAT, dt, t, L[12].cout, dt, stream));
-  APS_TRY(conv(L[13], t, nullptr, N, H, W, L[12].cout, 0, APS_CONV_DIRECT, dt, d0, c0, dt, stream));
-  // 1x1 heads
+  for (int l = 0; l < n_heads; ++l)
+    if (!logits[l]) return APS_ERR_NULL;
+  // dec0b with head0 fused into its epilogue (d0 feeds nothing else: it is not stored)
+  bool fused0 = false;
+  if (logit_dtype == dt) {
+    const aps_conv_layer& A = L[13];
+    const aps_conv_layer& Hd = L[kUnetConvs];
+    if (A.w && A.b && Hd.w && Hd.b && A.cin == L[12].cout && Hd.cin == A.cout && Hd.ksize == 1 &&
+        A.ksize == 3) {
+      const int r = aps_conv2d_fwd_head(t, nullptr, N, H, W, L[12].cout, 0, APS_CONV_DIRECT, A.w,
+                                        A.b, A.cout, A.relu, Hd.w, Hd.b, Hd.cout, dt, nullptr, 0,
+                                        logits[0], kstride[0], stream);
+      if (r == APS_OK) fused0 = true;
+      else if (r != APS_ERR_UNSUPPORTED) return r;
+    }
+  }
+  if (!fused0)
+    APS_TRY(conv(L[13], t, nullptr, N, H, W, L[12].cout, 0, APS_CONV_DIRECT, dt, d0, c0, dt, stream));
+  // remaining 1x1 heads
   const void* feats[4] = {d0, d1, d2, e3};
   const int fc[4] = {c0, c1, c2, c3};
   for (int l = 0; l < n_heads; ++l) {
-    if (!logits[l]) return APS_ERR_NULL;
+    if ((l == 0 && fused0) || (l == 1 && fused1)) continue;
     APS_TRY(conv(L[kUnetConvs + l], feats[l], nullptr, N, H >> l, W >> l, fc[l], 0,
                  APS_CONV_DIRECT, dt, logits[l], kstride[l], logit_dtype, stream));
   }

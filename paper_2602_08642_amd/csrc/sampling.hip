@@ -299,12 +299,28 @@ __device__ inline float mv_valid(int H, int W, int x, int y, float2 mv) {
   return (px >= -0.5f && px <= (float)W - 0.5f && py >= -0.5f && py <= (float)H - 0.5f) ? 1.f : 0.f;
 }
 
+// One pixel's feature row of C (8 or 16) channels as 16-byte stores.
 template <typename T>
-__device__ inline void store_feat(T* out, int c, float v);
+__device__ inline void store_row(T* dst, int C, const float* f);
 template <>
-__device__ inline void store_feat<float>(float* out, int c, float v) { out[c] = v; }
+__device__ inline void store_row<float>(float* dst, int C, const float* f) {
+  float4* d = reinterpret_cast<float4*>(dst);
+  d[0] = make_float4(f[0], f[1], f[2], f[3]);
+  d[1] = make_float4(f[4], f[5], f[6], f[7]);
+  if (C == 16) {
+    d[2] = make_float4(f[8], f[9], f[10], f[11]);
+    d[3] = make_float4(f[12], f[13], f[14], f[15]);
+  }
+}
 template <>
-__device__ inline void store_feat<uint16_t>(uint16_t* out, int c, float v) { out[c] = f2bf(v); }
+__device__ inline void store_row<uint16_t>(uint16_t* dst, int C, const float* f) {
+  u16x8* d = reinterpret_cast<u16x8*>(dst);
+  d[0] = u16x8{f2bf(f[0]), f2bf(f[1]), f2bf(f[2]), f2bf(f[3]),
+               f2bf(f[4]), f2bf(f[5]), f2bf(f[6]), f2bf(f[7])};
+  if (C == 16)
+    d[1] = u16x8{f2bf(f[8]), f2bf(f[9]), f2bf(f[10]), f2bf(f[11]),
+                 f2bf(f[12]), f2bf(f[13]), f2bf(f[14]), f2bf(f[15])};
+}
 
 // kind 0 (sampler input):   aux[0..6], then (temporal) tonemap(W prev) 3, valid 1; zero pad.
 // kind 1 (kernel predictor): aux[0..6], slog1p(L0) 3, s 1, then (temporal) slog1p(W prev) 3,
@@ -323,8 +339,12 @@ __global__ __launch_bounds__(256) void k_features(int kind, const float* __restr
   float f[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) f[c] = 0.f;
-#pragma unroll
-  for (int c = 0; c < 7; ++c) f[c] = aux[i * 8 + c];
+  {
+    const float4 a0 = reinterpret_cast<const float4*>(aux)[2 * i];
+    const float4 a1 = reinterpret_cast<const float4*>(aux)[2 * i + 1];
+    f[0] = a0.x; f[1] = a0.y; f[2] = a0.z; f[3] = a0.w;
+    f[4] = a1.x; f[5] = a1.y; f[6] = a1.z;
+  }
   int o = 7;
   if (kind == 1) {
     const float4 l = L0[i];
@@ -348,10 +368,7 @@ __global__ __launch_bounds__(256) void k_features(int kind, const float* __restr
     }
     f[o + 3] = mv_valid(H, W, x, y, m);
   }
-  T* dst = out + i * C;
-#pragma unroll
-  for (int c = 0; c < 16; ++c)
-    if (c < C) store_feat<T>(dst, c, f[c]);
+  store_row<T>(out + i * C, C, f);
 }
 
 // ======================================================================== backward
@@ -683,7 +700,7 @@ int aps_assemble_features(int kind, const float* aux, const float* L0, const flo
   if (kind == APS_FEAT_KERNEL && (!L0 || !s)) return APS_ERR_NULL;
   if (prev && !mv) return APS_ERR_NULL;
   const int need = (kind == APS_FEAT_KERNEL ? 11 : 7) + (prev ? 4 : 0);
-  if (C < need || C > 16) return APS_ERR_SHAPE;
+  if (C < need || (C != 8 && C != 16)) return APS_ERR_SHAPE;  // rows are 16-byte vectors
   const size_t npix = (size_t)N * H * W;
   if (npix == 0) return APS_OK;
   const int blocks = (int)((npix + 255) / 256);

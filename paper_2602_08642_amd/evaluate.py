@@ -46,7 +46,8 @@ def load_weights(path):
 
 
 def run(steps=300, batch=4, frames=8, lr=1e-3, eval_seeds=tuple(range(10000, 10008)),
-        budgets=(0.25, 0.3, 0.35, 0.4, 0.5), device="cuda", cfg_name="c4", log=print, H=None):
+        budgets=(0.25, 0.3, 0.35, 0.4, 0.5, 0.6, 0.75, 1.0), device="cuda", cfg_name="c4", log=print,
+        H=None):
     cfg = pipeline.CONFIGS[cfg_name]
     if H is not None:
         cfg = dataclasses.replace(cfg, H=H, W=H)
@@ -79,6 +80,8 @@ def run(steps=300, batch=4, frames=8, lr=1e-3, eval_seeds=tuple(range(10000, 100
             break
     res["equal_error_uniform_budget"] = eq
     res["equal_error_sample_ratio"] = None if eq is None else eq / cfg.budget
+    if eq is None and all(s["psnr"] < target for s in sweep):
+        res["equal_error_sample_ratio_lower_bound"] = budgets[-1] / cfg.budget
     res["psnr_gain_db"] = res["learned"]["psnr"] - res["uniform"]["psnr"]
     return res, (dnet, knet_l, knet_u)
 

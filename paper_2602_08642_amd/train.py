@@ -180,6 +180,8 @@ class TrainConfig:
     n_train_clips: int = 64
     seed: int = 0
     log_every: int = 10
+    # one model covers a range of budgets (Sec. 6.3): B log-uniform in [lo, hi] per step
+    budget_range: tuple = (0.125, 1.0)
 
 
 def cosine_lr(step, total, peak):
@@ -206,12 +208,15 @@ def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, 
         cb = data[ci]
         prev, prev_ref, gate = None, None, None
         losses = []
+        lo, hi = tc.budget_range
+        bstep = float(math.exp(np.random.default_rng([tc.seed, step]).uniform(math.log(lo), math.log(hi))))
+        cfg_s = dataclasses.replace(cfg, budget=bstep)
         for t in range(tc.frames):
             pool = sample_pool(cb.ref[t], gen)
             pin = None if prev is None else _Gate.apply(prev, gate)
             mv = cb.mv[t] if prev is not None else None
             seed = 1_000_003 * step + t
-            out, s = frame_forward(dnet, knet, cfg, cb.aux[t], pin, mv, pool, seed, t, "relaxed",
+            out, s = frame_forward(dnet, knet, cfg_s, cb.aux[t], pin, mv, pool, seed, t, "relaxed",
                                    uniform=tc.uniform)
             loss = ag.TMOLoss.apply(out, pin, cb.ref[t], prev_ref, mv, cb.params)
             loss.backward(retain_graph=True)
@@ -241,7 +246,8 @@ def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, 
             for _, p, _ in net.params():
                 p.grad = None
         lval = float(torch.stack(losses).mean().item())
-        history.append(dict(step=step, loss=lval, grad_norm=math.sqrt(gn), lr=lr, skipped=not finite))
+        history.append(dict(step=step, loss=lval, grad_norm=math.sqrt(gn), lr=lr, budget=bstep,
+                            skipped=not finite))
         if step % tc.log_every == 0 or step == 1:
             log(f"step {step:4d} loss {lval:.5f} |g| {math.sqrt(gn):.3e} lr {lr:.2e} "
                 f"{time.time() - t0:.1f}s")

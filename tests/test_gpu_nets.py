@@ -1,0 +1,84 @@
+"""Network parity: the kernel-predictor U-Net and the sampler CNN through their C ABI entry
+points against the FP64 oracle, and the fused conv + 1x1 head against separate launches."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import procgen
+from oracle import density as odens
+from oracle import unet as ounet
+from tests._tol import rel_norm
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def ops():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2602_08642_amd import ops as o
+    return o
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.bfloat16, 2e-2)])
+@pytest.mark.parametrize("heads", [[43, 34, 25], [67, 58, 58, 49]])
+def test_unet_matches_oracle(ops, dtype, tol, heads):
+    spec = procgen.unet_spec(16, heads)
+    w = procgen.init_weights(spec, 11)
+    net = ops.Net(spec, w, dtype, DEV)
+    g = torch.Generator().manual_seed(1)
+    x = torch.randn(2, 48, 64, 16, generator=g)
+    x[..., 15] = 0
+    logits = ops.kernel_predict(net, x.to(DEV).to(dtype), heads, dtype)
+    # oracle on the values the GPU saw (bf16 inputs and weights widened exactly)
+    wq = {k: (torch.tensor(a).to(dtype).double(), torch.tensor(b).double()) for k, (a, b) in w.items()}
+    ref = ounet.unet_forward(x.to(dtype).double(), wq, len(heads))
+    for l, K in enumerate(heads):
+        e = rel_norm(logits[l][..., :K].float().cpu(), ref[l])
+        assert e < tol, (l, e)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("cout,K", [(32, 34), (32, 43), (64, 34), (64, 58)])
+def test_fused_head_bit_identical(ops, dtype, cout, K):
+    from paper_2602_08642_amd import _lib as L
+    g = torch.Generator().manual_seed(cout * 100 + K)
+    N, H, W, cin = 1, 40, 72, 64
+    x = torch.randn(N, H, W, cin, generator=g).to(DEV).to(dtype)
+    sa = dict(name="a", cin=cin, cout=cout, k=3, relu=True)
+    sh = dict(name="h", cin=cout, cout=K, k=1, relu=False)
+    wa = (torch.randn(cout, 3, 3, cin, generator=g) / math.sqrt(9 * cin)).numpy()
+    wh = (torch.randn(K, 1, 1, cout, generator=g) / math.sqrt(cout)).numpy()
+    net = ops.Net([sa, sh], {"a": (wa, np.random.default_rng(0).normal(size=cout).astype(np.float32) * 0.1),
+                             "h": (wh, np.random.default_rng(1).normal(size=K).astype(np.float32) * 0.1)},
+                  dtype, DEV)
+    _, pa, ba = net.layer("a")
+    _, ph, bh = net.layer("h")
+    ks = ops.round_kstride(K, dtype)
+    y = ops.conv2d(x, sa, pa, ba)
+    ref = ops.conv2d(y, sh, ph, bh, ldy=ks)
+    fused = torch.full((N, H, W, ks), 7.0, dtype=dtype, device=DEV)
+    ymain = torch.empty_like(y)
+    dt = L.APS_F32 if dtype == torch.float32 else L.APS_BF16
+    L.check(L.load().aps_conv2d_fwd_head(ops._p(x), None, N, H, W, cin, 0, L.APS_CONV_DIRECT, ops._p(pa),
+                                         ops._p(ba), cout, 1, ops._p(ph), ops._p(bh), K, dt,
+                                         ops._p(ymain), cout, ops._p(fused), ks, ops._stream()), "fused")
+    assert torch.equal(fused[..., :K], ref[..., :K])
+    assert torch.equal(ymain, y)
+
+
+def test_sampler_cnn_matches_oracle(ops):
+    spec = procgen.density_cnn_spec(16)
+    w = procgen.init_weights(spec, 5)
+    net = ops.Net(spec, w, torch.float32, DEV)
+    g = torch.Generator().manual_seed(2)
+    x = torch.rand(2, 40, 56, 16, generator=g)
+    z, s = ops.density_predict(net, x.to(DEV), 0.25)
+    layers = [(torch.tensor(w[l["name"]][0], dtype=torch.float64), torch.tensor(w[l["name"]][1], dtype=torch.float64),
+               l["relu"]) for l in spec]
+    zr = odens.cnn_forward(x.double(), layers)[..., 0]
+    assert rel_norm(z.cpu(), zr) < 1e-5
+    sr = odens.normalise(z.double().cpu(), 0.25)
+    assert rel_norm(s.cpu(), sr) < 1e-6
