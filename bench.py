@@ -198,7 +198,7 @@ def bench_config(name, steps, warmup, dev, seed=2602):
                  "stages_ms": {n: round(mean(v), 4) for n, v in zip(names, st_u)},
                  "what": "s = B everywhere, all-zero logits (box-weighted pyramid)"},
         roofline={"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                  "frac": round(achieved / peak, 4), "traffic": None,
+                  "frac": round(achieved / peak, 4), "traffic": measured_traffic(name),
                   "kernel": "k_conv (implicit-GEMM MFMA conv), all U-Net launches of one frame",
                   "algorithmic_flop_per_frame": flops},
         filter_roofline={"bound": "hbm", "achieved": round(fgbs, 1), "peak": PEAK["hbm_GBps"],
@@ -211,6 +211,36 @@ def bench_config(name, steps, warmup, dev, seed=2602):
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2602_08642_amd", "weights", "c4_trained.npz")
+CSRC = os.path.join(ROOT, "paper_2602_08642_amd", "csrc")
+TRAFFIC_SOURCES = ("aps_common.h", "conv.hip", "net.hip")
+
+
+def source_digest(names=TRAFFIC_SOURCES):
+    """Digest of the sources the U-Net's convolution launches are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(CSRC, n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config):
+    """HBM bytes per U-Net pass from the committed PMC summary of this configuration
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or None when there is none
+    or the convolution sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"unet_{config}_pmc_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":", 1)[0].strip() in ("digest", "traffic_bytes_per_frame"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("digest") != source_digest():
+        return None
+    return int(fields["traffic_bytes_per_frame"])
 
 
 def quality(dev, seeds=(10000, 10001, 10002, 10003), frames=8):

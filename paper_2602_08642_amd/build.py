@@ -16,7 +16,10 @@ LIB = os.path.join(HERE, "libaps.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I", os.path.join(ROOT, "include")]
+         "-I", os.path.join(ROOT, "include"),
+         # MFMA accumulators in ordinary VGPRs: without it the register allocator moves
+         # accumulator tuples between AGPRs inside the MFMA loops
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _compile(src):

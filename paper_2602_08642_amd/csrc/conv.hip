@@ -178,6 +178,85 @@ __device__ inline void store_out<uint16_t>(uint16_t* p, int ldy, int co0, int Co
   }
 }
 
+// Epilogue shared by the convolution kernels: bias, optional ReLU, store; with HEAD, the fused
+// 1x1 head.  acc[m][j] holds output rows row0 + j, channels 16 (cob TM + m) + 4 (lane / 16) + q,
+// pixel column tx0 + lane % 16.  Xs is the block's LDS tile, reused by the head's re-layout.
+template <typename T, typename TO, int TM, int TN, bool HEAD>
+__device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], int row0, int tx0,
+                                     int cob, int n, int lane, int wave, T* Xs) {
+  TO* y = static_cast<TO*>(a.y);
+  if constexpr (!HEAD) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int row = row0 + j, col = tx0 + (lane & 15);
+      if (row >= a.H || col >= a.W) continue;
+      TO* py = y + (((size_t)n * a.H + row) * a.W + col) * a.ldy;
+#pragma unroll
+      for (int m = 0; m < TM; ++m) {
+        const int co0 = (cob * TM + m) * 16 + 4 * (lane >> 4);
+        if (co0 >= a.Cout) continue;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float t = acc[m][j][q] + (co0 + q < a.Cout && a.bias ? a.bias[co0 + q] : 0.f);
+          v[q] = a.relu ? fmaxf(t, 0.f) : t;
+        }
+        store_out<TO>(py, a.ldy, co0, a.Cout, v);
+      }
+    }
+  } else {
+    // Fused 1x1 head on this layer's output (all Cout = 16 TM channels are in this block):
+    // each wave re-lays its row-j tile [16 px][16 TM ch] out through LDS as MFMA B fragments
+    // and multiplies it by the packed head weights, the same operands in the same order as
+    // the stand-alone 1x1 convolution of the stored tile.
+    constexpr int CC = TM * 16, YP = CC + (sizeof(T) == 2 ? 8 : 4);
+    T* Ys = Xs + wave * 16 * YP;
+    const T* hw = static_cast<const T*>(a.hw);
+    TO* hy = static_cast<TO*>(a.hy);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int row = row0 + j, col = tx0 + (lane & 15);
+      const bool inpx = row < a.H && col < a.W;
+#pragma unroll
+      for (int m = 0; m < TM; ++m) {
+        const int co0 = m * 16 + 4 * (lane >> 4);
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float t = acc[m][j][q] + (a.bias ? a.bias[co0 + q] : 0.f);
+          v[q] = a.relu ? fmaxf(t, 0.f) : t;
+          Ys[(lane & 15) * YP + co0 + q] = f2t<T>(v[q]);
+        }
+        if (a.store_main && inpx)
+          store_out<TO>(y + (((size_t)n * a.H + row) * a.W + col) * a.ldy, a.ldy, co0, a.Cout, v);
+      }
+      __syncthreads();
+      Frag<T> bf[TM / 2];
+#pragma unroll
+      for (int cc = 0; cc < TM / 2; ++cc) frag_load(bf[cc], Ys + (lane & 15) * YP + 32 * cc + 8 * (lane >> 4));
+#pragma unroll
+      for (int mh = 0; mh < 4; ++mh) {
+        if (mh * 16 >= a.hK) break;
+        f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int cc = 0; cc < TM / 2; ++cc) {
+          Frag<T> wf;
+          frag_load(wf, hw + ((((size_t)mh * (TM / 2)) + cc) * 64 + lane) * 8);
+          h = mma(wf, bf[cc], h);
+        }
+        const int k0 = mh * 16 + 4 * (lane >> 4);
+        if (inpx && k0 < a.hK) {
+          float v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = h[q] + (k0 + q < a.hK ? a.hb[k0 + q] : 0.f);
+          store_out<TO>(hy + (((size_t)n * a.H + row) * a.W + col) * a.hldy, a.hldy, k0, a.hK, v);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // CG = 8-channel input groups per pixel in the K layout.  CG = 4: K walks 32-channel chunks,
 // one tap per MFMA step.  CG = 1 or 2 (inputs of at most 8 or 16 channels, a single chunk): K
 // enumerates (tap, group) pairs, so one MFMA step covers 4 / CG taps and no MFMA work is
@@ -257,75 +336,182 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     __syncthreads();
   }
 
-  TO* y = static_cast<TO*>(a.y);
-  if constexpr (!HEAD) {
+  conv_epilogue<T, TO, TM, TN, HEAD>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
+}
+
+// ---- bf16 3x3 convolution with both MFMA operands in LDS ---------------------------------
+// Block: 4 waves stacked vertically, each owning TN output rows x 16 px; all four share the
+// block's TM m-tiles (16 TM output channels).  Per 32-channel chunk, the block's weight
+// fragments (TM x 9 fragments of 1 KB, one per m-tile and tap) and the input tile (4 TN + 2
+// rows x 18 px with the 1-px halo) sit in LDS.  The global loads of chunk c+1 are issued
+// before the MFMAs of chunk c and held in registers until the chunk's barrier, so the MFMA loop
+// waits on LDS reads only.  For each column offset dx, every input-row fragment is read once
+// and feeds the (up to) three output rows it contributes to: 3 TM A and TN + 2 B reads per
+// 3 TN TM MFMAs.
+
+// 8 channels [ci, ci+8) of conv-input pixel (iy, ix) after the mode's transform, as bf16 bits
+// (zero outside the image or beyond Cin).  Cx and C2 are multiples of 8.
+template <int MODE>
+__device__ inline u16x8 fetch8(const ConvArgs& a, int n, int iy, int ix, int ci) {
+  const u16x8 zero = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  if (iy < 0 || iy >= a.H || ix < 0 || ix >= a.W || ci >= a.Cx + a.C2) return zero;
+  const uint16_t* x = static_cast<const uint16_t*>(a.x);
+  if constexpr (MODE == APS_CONV_DIRECT)
+    return *reinterpret_cast<const u16x8*>(x + (((size_t)n * a.H + iy) * a.W + ix) * a.Cx + ci);
+  if constexpr (MODE == kModeReluMask) {
+    const size_t o = (((size_t)n * a.H + iy) * a.W + ix) * a.Cx + ci;
+    const u16x8 g = *reinterpret_cast<const u16x8*>(x + o);
+    const u16x8 y = *reinterpret_cast<const u16x8*>(static_cast<const uint16_t*>(a.x2) + o);
+    u16x8 r;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int row = ty0 + wave * TN + j, col = tx0 + (lane & 15);
-      if (row >= a.H || col >= a.W) continue;
-      TO* py = y + (((size_t)n * a.H + row) * a.W + col) * a.ldy;
+    for (int e = 0; e < 8; ++e) r[e] = bf2f(y[e]) > 0.f ? g[e] : (uint16_t)0;
+    return r;
+  }
+  if constexpr (MODE == APS_CONV_POOL2) {
+    const int W2 = 2 * a.W;
+    const uint16_t* p = x + (((size_t)n * 2 * a.H + 2 * iy) * W2 + 2 * ix) * a.Cx + ci;
+    const V8f q0 = load8(p), q1 = load8(p + a.Cx), q2 = load8(p + (size_t)W2 * a.Cx),
+              q3 = load8(p + (size_t)W2 * a.Cx + a.Cx);
+    u16x8 r;
 #pragma unroll
-      for (int m = 0; m < TM; ++m) {
-        const int co0 = (cob * TM + m) * 16 + 4 * (lane >> 4);
-        if (co0 >= a.Cout) continue;
-        float v[4];
+    for (int e = 0; e < 8; ++e) r[e] = f2bf(((q0.v[e] + q1.v[e]) + (q2.v[e] + q3.v[e])) * 0.25f);
+    return r;
+  }
+  if constexpr (MODE == APS_CONV_UP2_CAT) {
+    if (ci < a.Cx)
+      return *reinterpret_cast<const u16x8*>(x + (((size_t)n * (a.H / 2) + iy / 2) * (a.W / 2) + ix / 2) * a.Cx + ci);
+    return *reinterpret_cast<const u16x8*>(static_cast<const uint16_t*>(a.x2) +
+                                           (((size_t)n * a.H + iy) * a.W + ix) * a.C2 + (ci - a.Cx));
+  }
+  return zero;
+}
+
+template <int MODE, int TM, int TN, bool HEAD>
+__global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
+  constexpr int ROWS = 4 * TN, SH = ROWS + 2, SW = 18, PS = 40;
+  constexpr int NXV = SH * SW * 4, NXT = (NXV + 255) / 256;  // input 16-B vectors per chunk
+  constexpr int NAV = TM * 9 * 64, NAT = (NAV + 255) / 256;  // weight 16-B vectors per chunk
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[SH * SW * PS];
+  __shared__ __attribute__((aligned(16))) uint16_t As[NAV * 8];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tx0 = (blockIdx.x % a.ntx) * 16, ty0 = (blockIdx.x / a.ntx) * ROWS;
+  const int cob = blockIdx.y, n = blockIdx.z;
+  const uint16_t* wp = static_cast<const uint16_t*>(a.wp);
+
+  u16x8 px[NXT], pa[NAT];
+  auto fetch = [&](int c) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float t = acc[m][j][q] + (co0 + q < a.Cout && a.bias ? a.bias[co0 + q] : 0.f);
-          v[q] = a.relu ? fmaxf(t, 0.f) : t;
-        }
-        store_out<TO>(py, a.ldy, co0, a.Cout, v);
+    for (int k = 0; k < NXT; ++k) {
+      const int it = tid + 256 * k;
+      if (it < NXV) {
+        const int g = it & 3, p = it >> 2, r = p / SW, col = p - r * SW;
+        px[k] = fetch8<MODE>(a, n, ty0 - 1 + r, tx0 - 1 + col, c * kChunk + g * 8);
       }
     }
+#pragma unroll
+    for (int k = 0; k < NAT; ++k) {
+      const int v = tid + 256 * k;
+      if (v < NAV) {
+        const int f = v >> 6, m = f / 9, tap = f - 9 * m;
+        pa[k] = *reinterpret_cast<const u16x8*>(
+            wp + (((((size_t)cob * TM + m) * 9 + tap) * a.nchunk + c) * 64 + (v & 63)) * 8);
+      }
+    }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int k = 0; k < NXT; ++k) {
+      const int it = tid + 256 * k;
+      if (it < NXV) *reinterpret_cast<u16x8*>(Xs + (it >> 2) * PS + (it & 3) * 8) = px[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NAT; ++k) {
+      const int v = tid + 256 * k;
+      if (v < NAV) *reinterpret_cast<u16x8*>(As + v * 8) = pa[k];
+    }
+  };
+
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  fetch(0);
+  put();
+  __syncthreads();
+  for (int c = 0; c < a.nchunk; ++c) {
+    const bool more = c + 1 < a.nchunk;
+    if (more) fetch(c + 1);
+    // pooled inputs are averaged now rather than holding four raw loads across the MFMAs
+    if constexpr (MODE == APS_CONV_POOL2) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      __builtin_amdgcn_sched_barrier(0);  // keep one dx step's fragments live at a time
+      Frag<uint16_t> A[3][TM];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int m = 0; m < TM; ++m) frag_load(A[dy][m], As + ((m * 9 + dy * 3 + dx) * 64 + lane) * 8);
+#pragma unroll
+      for (int ir = 0; ir < TN + 2; ++ir) {
+        Frag<uint16_t> B;
+        frag_load(B, Xs + ((wave * TN + ir) * SW + (lane & 15) + dx) * PS + (lane >> 4) * 8);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const int j = ir - dy;
+          if (j >= 0 && j < TN) {
+#pragma unroll
+            for (int m = 0; m < TM; ++m) acc[m][j] = mma(A[dy][m], B, acc[m][j]);
+          }
+        }
+      }
+    }
+    if (more) {
+      __syncthreads();
+      put();
+      __syncthreads();
+    }
+  }
+  if constexpr (HEAD) __syncthreads();  // the head's re-layout reuses Xs
+  conv_epilogue<uint16_t, uint16_t, TM, TN, HEAD>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
+}
+
+// Launch k_conv_lds for a bf16 3x3 convolution with bf16 output whose input channels fill
+// 32-channel chunks (Cin > 16); TM = 2 for Cout <= 32, else 4 with ceil(Cout / 64) channel
+// blocks; 8-row blocks for small problems.
+template <int MODE, bool HEAD>
+void launch_conv_lds_m(const ConvArgs& a, hipStream_t st) {
+  ConvArgs b = a;
+  b.ntx = (a.W + 15) / 16;
+  const bool small = (size_t)a.N * a.H * a.W < 64 * 64 * 8;
+  const int rows = small ? 8 : 16;
+  dim3 grid(b.ntx * ((a.H + rows - 1) / rows), a.Cout <= 32 ? 1 : (a.Cout + 63) / 64, a.N);
+  if (a.Cout <= 32) {
+    if (small) k_conv_lds<MODE, 2, 2, HEAD><<<grid, 256, 0, st>>>(b);
+    else k_conv_lds<MODE, 2, 4, HEAD><<<grid, 256, 0, st>>>(b);
   } else {
-    // Fused 1x1 head on this layer's output (all Cout = 16 TM channels are in this block):
-    // each wave re-lays its row-j tile [16 px][16 TM ch] out through LDS as MFMA B fragments
-    // and multiplies it by the packed head weights, the same operands in the same order as
-    // the stand-alone 1x1 convolution of the stored tile.
-    constexpr int CC = TM * 16, YP = CC + (sizeof(T) == 2 ? 8 : 4);
-    T* Ys = Xs + wave * 16 * YP;
-    const T* hw = static_cast<const T*>(a.hw);
-    TO* hy = static_cast<TO*>(a.hy);
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int row = ty0 + wave * TN + j, col = tx0 + (lane & 15);
-      const bool inpx = row < a.H && col < a.W;
-#pragma unroll
-      for (int m = 0; m < TM; ++m) {
-        const int co0 = m * 16 + 4 * (lane >> 4);
-        float v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float t = acc[m][j][q] + (a.bias ? a.bias[co0 + q] : 0.f);
-          v[q] = a.relu ? fmaxf(t, 0.f) : t;
-          Ys[(lane & 15) * YP + co0 + q] = f2t<T>(v[q]);
-        }
-        if (a.store_main && inpx)
-          store_out<TO>(y + (((size_t)n * a.H + row) * a.W + col) * a.ldy, a.ldy, co0, a.Cout, v);
-      }
-      __syncthreads();
-      Frag<T> bf[TM / 2];
-#pragma unroll
-      for (int cc = 0; cc < TM / 2; ++cc) frag_load(bf[cc], Ys + (lane & 15) * YP + 32 * cc + 8 * (lane >> 4));
-#pragma unroll
-      for (int mh = 0; mh < 4; ++mh) {
-        if (mh * 16 >= a.hK) break;
-        f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int cc = 0; cc < TM / 2; ++cc) {
-          Frag<T> wf;
-          frag_load(wf, hw + ((((size_t)mh * (TM / 2)) + cc) * 64 + lane) * 8);
-          h = mma(wf, bf[cc], h);
-        }
-        const int k0 = mh * 16 + 4 * (lane >> 4);
-        if (inpx && k0 < a.hK) {
-          float v[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = h[q] + (k0 + q < a.hK ? a.hb[k0 + q] : 0.f);
-          store_out<TO>(hy + (((size_t)n * a.H + row) * a.W + col) * a.hldy, a.hldy, k0, a.hK, v);
-        }
-      }
-      __syncthreads();
+    if (small) k_conv_lds<MODE, 4, 2, HEAD><<<grid, 256, 0, st>>>(b);
+    else k_conv_lds<MODE, 4, 4, HEAD><<<grid, 256, 0, st>>>(b);
+  }
+}
+
+// false: the configuration is not covered (the caller uses k_conv)
+template <bool HEAD>
+bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
+  if (a.Cout <= 16) return false;
+  if constexpr (HEAD) {
+    if (a.mode != APS_CONV_DIRECT) return false;
+    launch_conv_lds_m<APS_CONV_DIRECT, true>(a, st);
+    return true;
+  } else {
+    switch (a.mode) {
+      case APS_CONV_DIRECT: launch_conv_lds_m<APS_CONV_DIRECT, false>(a, st); return true;
+      case APS_CONV_POOL2: launch_conv_lds_m<APS_CONV_POOL2, false>(a, st); return true;
+      case APS_CONV_UP2_CAT: launch_conv_lds_m<APS_CONV_UP2_CAT, false>(a, st); return true;
+      case kModeReluMask: launch_conv_lds_m<kModeReluMask, false>(a, st); return true;
+      default: return false;
     }
   }
 }
@@ -397,6 +583,9 @@ void launch_conv(const ConvArgs& a, hipStream_t st) {
 // 3x3 conv (Cout = 16 TM, one block covers all of it) with its 1x1 head in the epilogue.
 template <typename T, int TM>
 void launch_conv_head(const ConvArgs& a, hipStream_t st) {
+  if constexpr (sizeof(T) == 2) {
+    if (launch_conv_lds<true>(a, st)) return;
+  }
   const bool big = (size_t)a.H * a.W >= 64 * 64;
   const int TN = big ? 4 : 2, TH = 4 * TN;
   ConvArgs b = a;
@@ -408,6 +597,9 @@ void launch_conv_head(const ConvArgs& a, hipStream_t st) {
 
 template <typename T, typename TO, int KS, int CG>
 void dispatch_tiles(const ConvArgs& a, hipStream_t st) {
+  if constexpr (sizeof(T) == 2 && sizeof(TO) == 2 && KS == 3 && CG == 4) {
+    if (launch_conv_lds<false>(a, st)) return;
+  }
   const bool big = (size_t)a.H * a.W >= 64 * 64;
   if (a.Cout <= 16) {
     if (big) launch_conv<T, TO, KS, 1, 4, CG>(a, st); else launch_conv<T, TO, KS, 1, 2, CG>(a, st);

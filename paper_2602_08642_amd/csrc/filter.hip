@@ -12,8 +12,7 @@ using namespace aps::flt;
 
 namespace {
 
-// STAGE: the tile's logits go through LDS (coalesced rows) instead of per-thread loads.
-template <int KD, int KU, int KT, bool HU, bool HT, typename LT, bool STAGE>
+template <int KD, int KU, int KT, bool HU, bool HT, typename LT>
 __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   using G = Geo<KD, KU, KT, HU, HT>;
   constexpr int NK = G::NK;
@@ -22,7 +21,6 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   __shared__ float4 Ls[G::LS];
   __shared__ float4 Cs[G::CS];
   __shared__ float4 Ts[G::PS];
-  extern __shared__ uint4 zdyn[];
 
   const int H = a.H, W = a.W;
   const int tid = threadIdx.x, tx = tid % TW, ty = tid / TW;
@@ -31,16 +29,13 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   const bool in = x < W && y < H;
 
   float z[NKP];
-  if (STAGE) {
-    stage_logits<LT>(a, reinterpret_cast<LT*>(zdyn), x0, y0, n);
-  } else if (in) {
+  if (in) {
     const LT* lp = static_cast<const LT*>(a.logits) + (((size_t)n * H + y) * W + x) * a.kstride;
     LogitVec<LT>::template load<NKP>(lp, z);
   }
   stage_tiles<G>(a, Ls, Cs, Ts, x0, y0, n, HU, HT);
   __syncthreads();
   if (!in) return;
-  if (STAGE) LogitVec<LT>::template load<NKP>(reinterpret_cast<const LT*>(zdyn) + (size_t)tid * a.kstride, z);
 
   float m = z[0];
 #pragma unroll
@@ -72,19 +67,10 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
 template <int KD, int KU, int KT, typename LT>
 int launch_level_t(const LevelArgs& a, bool hu, bool ht, int N, hipStream_t st) {
   dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, N);
-  // stage the logits through LDS when the tile's logits fit in 48 KB (all configured sizes)
-  const size_t zb = (size_t)TW * TH * a.kstride * sizeof(LT);
-  if (zb <= 48 * 1024) {
-    if (hu && ht) k_level<KD, KU, KT, true, true, LT, true><<<grid, 256, zb, st>>>(a);
-    else if (hu) k_level<KD, KU, KT, true, false, LT, true><<<grid, 256, zb, st>>>(a);
-    else if (ht) k_level<KD, KU, KT, false, true, LT, true><<<grid, 256, zb, st>>>(a);
-    else k_level<KD, KU, KT, false, false, LT, true><<<grid, 256, zb, st>>>(a);
-  } else {
-    if (hu && ht) k_level<KD, KU, KT, true, true, LT, false><<<grid, 256, 0, st>>>(a);
-    else if (hu) k_level<KD, KU, KT, true, false, LT, false><<<grid, 256, 0, st>>>(a);
-    else if (ht) k_level<KD, KU, KT, false, true, LT, false><<<grid, 256, 0, st>>>(a);
-    else k_level<KD, KU, KT, false, false, LT, false><<<grid, 256, 0, st>>>(a);
-  }
+  if (hu && ht) k_level<KD, KU, KT, true, true, LT><<<grid, 256, 0, st>>>(a);
+  else if (hu) k_level<KD, KU, KT, true, false, LT><<<grid, 256, 0, st>>>(a);
+  else if (ht) k_level<KD, KU, KT, false, true, LT><<<grid, 256, 0, st>>>(a);
+  else k_level<KD, KU, KT, false, false, LT><<<grid, 256, 0, st>>>(a);
   APS_LAUNCH_CHECK();
   return APS_OK;
 }

@@ -86,23 +86,6 @@ __device__ inline float4 warp_at(const float4* __restrict__ prev, const float2* 
                      t.gy * (t.gx * a.z + t.fx * b.z) + t.fy * (t.gx * c.z + t.fx * d.z), 0.f);
 }
 
-// Copy the tile's logits (TH rows of up to TW pixels, kstride values each; each row is one
-// contiguous span in NHWC) into LDS with coalesced 16-byte loads.  Pixel (tx, ty) of the tile
-// lands at Zs + (ty * TW + tx) * kstride.  kstride * sizeof(LT) is a multiple of 16.
-template <typename LT>
-__device__ inline void stage_logits(const LevelArgs& a, LT* Zs, int x0, int y0, int n) {
-  constexpr int VE = 16 / sizeof(LT);
-  const int H = a.H, W = a.W, ks = a.kstride;
-  const int rows = min(TH, H - y0);
-  const int vpr = min(TW, W - x0) * ks / VE;  // vectors per tile row
-  const LT* base = static_cast<const LT*>(a.logits);
-  for (int k = threadIdx.x; k < rows * vpr; k += 256) {
-    const int r = k / vpr, v = k - r * vpr;
-    const uint4* src = reinterpret_cast<const uint4*>(base + (((size_t)n * H + y0 + r) * W + x0) * ks);
-    reinterpret_cast<uint4*>(Zs + (size_t)r * TW * ks)[v] = src[v];
-  }
-}
-
 // Tile geometry of one level kernel instantiation.
 template <int KD, int KU, int KT, bool HU, bool HT>
 struct Geo {
