@@ -22,6 +22,7 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 struct LevelPtrs {
   float4* p[APS_MAX_LEVELS];
@@ -38,6 +39,11 @@ __device__ __host__ inline uint16_t f2bf(float f) {
 }
 __device__ __host__ inline float bf2f(uint16_t h) {
   return __builtin_bit_cast(float, ((uint32_t)h) << 16);
+}
+// four floats -> four bf16 with the hardware packed conversion (round to nearest even)
+__device__ inline u16x4 f2bf4(float a, float b, float c, float d) {
+  typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+  return __builtin_bit_cast(u16x4, __builtin_convertvector(f32x4{a, b, c, d}, bf16x4_t));
 }
 template <typename T>
 __device__ inline T f2t(float v);

@@ -170,7 +170,7 @@ __device__ inline void store_out<float>(float* p, int ldy, int co0, int Cout, co
 template <>
 __device__ inline void store_out<uint16_t>(uint16_t* p, int ldy, int co0, int Cout, const float* v) {
   if ((ldy & 3) == 0 && co0 + 4 <= ldy) {
-    *reinterpret_cast<u16x4*>(p + co0) = u16x4{f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+    *reinterpret_cast<u16x4*>(p + co0) = f2bf4(v[0], v[1], v[2], v[3]);
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -181,14 +181,23 @@ __device__ inline void store_out<uint16_t>(uint16_t* p, int ldy, int co0, int Co
 // Epilogue shared by the convolution kernels: bias, optional ReLU, store; with HEAD, the fused
 // 1x1 head.  acc[m][j] holds output rows row0 + j, channels 16 (cob TM + m) + 4 (lane / 16) + q,
 // pixel column tx0 + lane % 16.  Xs is the block's LDS tile, reused by the head's re-layout.
-template <typename T, typename TO, int TM, int TN, bool HEAD>
+template <typename T, typename TO, int TM, int TN, bool HEAD, bool BIAS_IN_ACC = false>
 __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], int row0, int tx0,
                                      int cob, int n, int lane, int wave, T* Xs) {
   TO* y = static_cast<TO*>(a.y);
+  const int col = tx0 + (lane & 15);
+  float bv[TM][4];  // this lane's bias values, loaded once
+#pragma unroll
+  for (int m = 0; m < TM; ++m) {
+    const int co0 = (cob * TM + m) * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      bv[m][q] = !BIAS_IN_ACC && co0 + q < a.Cout && a.bias ? a.bias[co0 + q] : 0.f;
+  }
   if constexpr (!HEAD) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      const int row = row0 + j, col = tx0 + (lane & 15);
+      const int row = row0 + j;
       if (row >= a.H || col >= a.W) continue;
       TO* py = y + (((size_t)n * a.H + row) * a.W + col) * a.ldy;
 #pragma unroll
@@ -198,7 +207,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
         float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          float t = acc[m][j][q] + (co0 + q < a.Cout && a.bias ? a.bias[co0 + q] : 0.f);
+          const float t = acc[m][j][q] + bv[m][q];
           v[q] = a.relu ? fmaxf(t, 0.f) : t;
         }
         store_out<TO>(py, a.ldy, co0, a.Cout, v);
@@ -215,7 +224,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
     TO* hy = static_cast<TO*>(a.hy);
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      const int row = row0 + j, col = tx0 + (lane & 15);
+      const int row = row0 + j;
       const bool inpx = row < a.H && col < a.W;
 #pragma unroll
       for (int m = 0; m < TM; ++m) {
@@ -223,7 +232,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
         float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float t = acc[m][j][q] + (a.bias ? a.bias[co0 + q] : 0.f);
+          const float t = acc[m][j][q] + bv[m][q];
           v[q] = a.relu ? fmaxf(t, 0.f) : t;
           Ys[(lane & 15) * YP + co0 + q] = f2t<T>(v[q]);
         }
@@ -349,42 +358,10 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 // and feeds the (up to) three output rows it contributes to: 3 TM A and TN + 2 B reads per
 // 3 TN TM MFMAs.
 
-// 8 channels [ci, ci+8) of conv-input pixel (iy, ix) after the mode's transform, as bf16 bits
-// (zero outside the image or beyond Cin).  Cx and C2 are multiples of 8.
-template <int MODE>
-__device__ inline u16x8 fetch8(const ConvArgs& a, int n, int iy, int ix, int ci) {
-  const u16x8 zero = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-  if (iy < 0 || iy >= a.H || ix < 0 || ix >= a.W || ci >= a.Cx + a.C2) return zero;
-  const uint16_t* x = static_cast<const uint16_t*>(a.x);
-  if constexpr (MODE == APS_CONV_DIRECT)
-    return *reinterpret_cast<const u16x8*>(x + (((size_t)n * a.H + iy) * a.W + ix) * a.Cx + ci);
-  if constexpr (MODE == kModeReluMask) {
-    const size_t o = (((size_t)n * a.H + iy) * a.W + ix) * a.Cx + ci;
-    const u16x8 g = *reinterpret_cast<const u16x8*>(x + o);
-    const u16x8 y = *reinterpret_cast<const u16x8*>(static_cast<const uint16_t*>(a.x2) + o);
-    u16x8 r;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = bf2f(y[e]) > 0.f ? g[e] : (uint16_t)0;
-    return r;
-  }
-  if constexpr (MODE == APS_CONV_POOL2) {
-    const int W2 = 2 * a.W;
-    const uint16_t* p = x + (((size_t)n * 2 * a.H + 2 * iy) * W2 + 2 * ix) * a.Cx + ci;
-    const V8f q0 = load8(p), q1 = load8(p + a.Cx), q2 = load8(p + (size_t)W2 * a.Cx),
-              q3 = load8(p + (size_t)W2 * a.Cx + a.Cx);
-    u16x8 r;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = f2bf(((q0.v[e] + q1.v[e]) + (q2.v[e] + q3.v[e])) * 0.25f);
-    return r;
-  }
-  if constexpr (MODE == APS_CONV_UP2_CAT) {
-    if (ci < a.Cx)
-      return *reinterpret_cast<const u16x8*>(x + (((size_t)n * (a.H / 2) + iy / 2) * (a.W / 2) + ix / 2) * a.Cx + ci);
-    return *reinterpret_cast<const u16x8*>(static_cast<const uint16_t*>(a.x2) +
-                                           (((size_t)n * a.H + iy) * a.W + ix) * a.C2 + (ci - a.Cx));
-  }
-  return zero;
-}
+constexpr uint32_t kNoPixel = 0xffffffffu;
+
+// bf16 y > 0 (positive, finite or +inf), decided on the bits
+__device__ inline bool bf_pos(uint16_t b) { return (int16_t)b > 0 && (b & 0x7fffu) <= 0x7f80u; }
 
 template <int MODE, int TM, int TN, bool HEAD>
 __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
@@ -397,33 +374,81 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int tx0 = (blockIdx.x % a.ntx) * 16, ty0 = (blockIdx.x / a.ntx) * ROWS;
   const int cob = blockIdx.y, n = blockIdx.z;
+  const uint16_t* x = static_cast<const uint16_t*>(a.x);
+  const uint16_t* x2 = static_cast<const uint16_t*>(a.x2);
   const uint16_t* wp = static_cast<const uint16_t*>(a.wp);
+  const int Cin = a.Cx + a.C2;
+  // This thread stages channel group g (8 channels) of tile pixels (tid / 4) + 64 k.  Their
+  // element offsets at chunk 0 are computed once (32-bit; kNoPixel outside the image):
+  // xo into x (for POOL2 the top-left of the 2x2 window, for UP2_CAT the parent pixel of the
+  // coarse tensor), so into the skip tensor x2 (UP2_CAT only).
+  const int g8 = (tid & 3) * 8;
+  uint32_t xo[NXT], so[MODE == APS_CONV_UP2_CAT ? NXT : 1];
+#pragma unroll
+  for (int k = 0; k < NXT; ++k) {
+    const int p = (tid >> 2) + 64 * k, r = p / SW, col = p - r * SW;
+    const int iy = ty0 - 1 + r, ix = tx0 - 1 + col;
+    const bool in = p < SH * SW && iy >= 0 && iy < a.H && ix >= 0 && ix < a.W;
+    uint32_t o = kNoPixel;
+    if (in) {
+      if constexpr (MODE == APS_CONV_POOL2)
+        o = (uint32_t)((((size_t)n * 2 * a.H + 2 * iy) * (2 * a.W) + 2 * ix) * a.Cx + g8);
+      else if constexpr (MODE == APS_CONV_UP2_CAT)
+        o = (uint32_t)((((size_t)n * (a.H / 2) + iy / 2) * (a.W / 2) + ix / 2) * a.Cx + g8);
+      else
+        o = (uint32_t)((((size_t)n * a.H + iy) * a.W + ix) * a.Cx + g8);
+    }
+    xo[k] = o;
+    if constexpr (MODE == APS_CONV_UP2_CAT)
+      so[k] = in ? (uint32_t)((((size_t)n * a.H + iy) * a.W + ix) * a.C2 + g8) : kNoPixel;
+  }
+  // weights: vector v = tid + 256 k of the chunk is fragment f = v / 64 (m-tile f / 9, tap f % 9)
+  const uint32_t wo = (uint32_t)((((size_t)cob * TM * 9 + wave) * a.nchunk) * 512 + lane * 8);
+  const uint32_t wstep = (uint32_t)(4 * a.nchunk * 512);
 
   u16x8 px[NXT], pa[NAT];
   auto fetch = [&](int c) {
+    const int cb = c * kChunk;
+    const bool in_ch = cb + g8 < Cin;
 #pragma unroll
     for (int k = 0; k < NXT; ++k) {
-      const int it = tid + 256 * k;
-      if (it < NXV) {
-        const int g = it & 3, p = it >> 2, r = p / SW, col = p - r * SW;
-        px[k] = fetch8<MODE>(a, n, ty0 - 1 + r, tx0 - 1 + col, c * kChunk + g * 8);
+      u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (xo[k] != kNoPixel && in_ch) {
+        if constexpr (MODE == APS_CONV_DIRECT) {
+          v = *reinterpret_cast<const u16x8*>(x + (xo[k] + cb));
+        } else if constexpr (MODE == kModeReluMask) {
+          // x = dLoss/dy, x2 = the layer's post-ReLU output: dy where y > 0
+          const u16x8 gr = *reinterpret_cast<const u16x8*>(x + (xo[k] + cb));
+          const u16x8 yv = *reinterpret_cast<const u16x8*>(x2 + (xo[k] + cb));
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = bf_pos(yv[e]) ? gr[e] : (uint16_t)0;
+        } else if constexpr (MODE == APS_CONV_POOL2) {
+          const uint32_t rs = (uint32_t)(2 * a.W * a.Cx);
+          const uint32_t o = xo[k] + cb;
+          const V8f q0 = load8(x + o), q1 = load8(x + (o + a.Cx)), q2 = load8(x + (o + rs)),
+                    q3 = load8(x + (o + rs + a.Cx));
+          float r[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) r[e] = ((q0.v[e] + q1.v[e]) + (q2.v[e] + q3.v[e])) * 0.25f;
+          const u16x4 lo = f2bf4(r[0], r[1], r[2], r[3]), hi = f2bf4(r[4], r[5], r[6], r[7]);
+          v = u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        } else {  // APS_CONV_UP2_CAT: channels [0, Cx) from the coarse tensor, then the skip
+          if (cb + g8 < a.Cx) v = *reinterpret_cast<const u16x8*>(x + (xo[k] + cb));
+          else v = *reinterpret_cast<const u16x8*>(x2 + (so[k] + (cb - a.Cx)));
+        }
       }
+      px[k] = v;
     }
 #pragma unroll
-    for (int k = 0; k < NAT; ++k) {
-      const int v = tid + 256 * k;
-      if (v < NAV) {
-        const int f = v >> 6, m = f / 9, tap = f - 9 * m;
-        pa[k] = *reinterpret_cast<const u16x8*>(
-            wp + (((((size_t)cob * TM + m) * 9 + tap) * a.nchunk + c) * 64 + (v & 63)) * 8);
-      }
-    }
+    for (int k = 0; k < NAT; ++k)
+      if (tid + 256 * k < NAV)
+        pa[k] = *reinterpret_cast<const u16x8*>(wp + (wo + k * wstep + c * 512));
   };
   auto put = [&]() {
 #pragma unroll
     for (int k = 0; k < NXT; ++k) {
-      const int it = tid + 256 * k;
-      if (it < NXV) *reinterpret_cast<u16x8*>(Xs + (it >> 2) * PS + (it & 3) * 8) = px[k];
+      const int p = (tid >> 2) + 64 * k;
+      if (p < SH * SW) *reinterpret_cast<u16x8*>(Xs + p * PS + g8) = px[k];
     }
 #pragma unroll
     for (int k = 0; k < NAT; ++k) {
@@ -432,11 +457,16 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
     }
   };
 
+  // accumulators start at the bias
   f32x4 acc[TM][TN];
 #pragma unroll
-  for (int m = 0; m < TM; ++m)
+  for (int m = 0; m < TM; ++m) {
+    f32x4 b0 = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int co0 = (cob * TM + m) * 16 + 4 * (lane >> 4);
+    if (a.bias && co0 < a.Cout) b0 = *reinterpret_cast<const f32x4*>(a.bias + co0);
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TN; ++j) acc[m][j] = b0;
+  }
 
   fetch(0);
   put();
@@ -474,8 +504,28 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
       __syncthreads();
     }
   }
-  if constexpr (HEAD) __syncthreads();  // the head's re-layout reuses Xs
-  conv_epilogue<uint16_t, uint16_t, TM, TN, HEAD>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
+  if constexpr (HEAD) {
+    __syncthreads();  // the head's re-layout reuses Xs
+    conv_epilogue<uint16_t, uint16_t, TM, TN, true, true>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
+  } else {
+    // bf16 store of 4 channels per lane; ReLU on the rounded bits (round-to-nearest-even keeps
+    // the sign, so this equals rounding max(v, 0)).  Cout % 16 == 0 and ldy % 4 == 0 (host).
+    uint16_t* y = static_cast<uint16_t*>(a.y);
+    const int col = tx0 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int row = ty0 + wave * TN + j;
+      if (row >= a.H || col >= a.W) continue;
+      uint16_t* py = y + (((size_t)n * a.H + row) * a.W + col) * a.ldy + cob * TM * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int m = 0; m < TM; ++m) {
+        if ((cob * TM + m) * 16 >= a.Cout) continue;
+        s16x4 h = __builtin_bit_cast(s16x4, f2bf4(acc[m][j][0], acc[m][j][1], acc[m][j][2], acc[m][j][3]));
+        if (a.relu) h = __builtin_elementwise_max(h, s16x4{0, 0, 0, 0});
+        *reinterpret_cast<s16x4*>(py + m * 16) = h;
+      }
+    }
+  }
 }
 
 // Launch k_conv_lds for a bf16 3x3 convolution with bf16 output whose input channels fill
@@ -500,7 +550,13 @@ void launch_conv_lds_m(const ConvArgs& a, hipStream_t st) {
 // false: the configuration is not covered (the caller uses k_conv)
 template <bool HEAD>
 bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
-  if (a.Cout <= 16) return false;
+  if (a.Cout <= 16 || a.Cout % 16 || a.ldy % 4) return false;
+  // the kernel addresses its inputs with 32-bit element offsets
+  const size_t px = (size_t)a.N * a.H * a.W;
+  const size_t ex = a.mode == APS_CONV_POOL2 ? 4 * px * a.Cx
+                    : a.mode == APS_CONV_UP2_CAT ? px / 4 * a.Cx : px * a.Cx;
+  const size_t e2 = a.mode == APS_CONV_UP2_CAT ? px * a.C2 : 0;
+  if ((ex > e2 ? ex : e2) + kChunk >= ((size_t)1 << 31)) return false;
   if constexpr (HEAD) {
     if (a.mode != APS_CONV_DIRECT) return false;
     launch_conv_lds_m<APS_CONV_DIRECT, true>(a, st);
