@@ -34,6 +34,7 @@ SIGNATURES = {
     "aps_conv_pack_weights": (I, [P, I, I, I, I, P, P]),
     "aps_conv2d_fwd": (I, [P, P, I, I, I, I, I, I, P, P, I, I, I, I, P, I, I, P]),
     "aps_conv2d_fwd_head": (I, [P, P, I, I, I, I, I, I, P, P, I, I, P, P, I, I, P, I, P, I, P]),
+    "aps_conv2d_fwd_pool": (I, [P, P, I, I, I, I, I, I, P, P, I, I, I, P, P, P]),
     "aps_normalize_workspace_size": (SZ, [I, I, I]),
     "aps_normalize_density": (I, [P, I, I, I, F, F, P, P, SZ, P, P]),
     "aps_density_predict_workspace_size": (SZ, [I, I, I, I, I]),

@@ -33,6 +33,8 @@ struct ConvArgs {
   int hK;
   void* hy;
   int hldy, store_main;
+  // optional 2x2 average pool of the (bf16-rounded) output, [N, H/2, W/2, Cout] (k_conv_lds)
+  void* pool;
 };
 
 // ---- 8-element vectors of the storage type ---------------------------------------------
@@ -215,13 +217,28 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
     }
   } else {
     // Fused 1x1 head on this layer's output (all Cout = 16 TM channels are in this block):
-    // each wave re-lays its row-j tile [16 px][16 TM ch] out through LDS as MFMA B fragments
-    // and multiplies it by the packed head weights, the same operands in the same order as
-    // the stand-alone 1x1 convolution of the stored tile.
+    // each wave re-lays its row-j tile [16 px][16 TM ch] out through its own LDS region as MFMA
+    // B fragments and multiplies it by the packed head weights (held in registers), the same
+    // operands in the same order as the stand-alone 1x1 convolution of the stored tile.  The
+    // regions are per wave, so after the caller's barrier only wave-local ordering is needed.
     constexpr int CC = TM * 16, YP = CC + (sizeof(T) == 2 ? 8 : 4);
     T* Ys = Xs + wave * 16 * YP;
     const T* hw = static_cast<const T*>(a.hw);
     TO* hy = static_cast<TO*>(a.hy);
+    Frag<T> hwf[4][TM / 2];
+#pragma unroll
+    for (int mh = 0; mh < 4; ++mh)
+#pragma unroll
+      for (int cc = 0; cc < TM / 2; ++cc)
+        if (mh * 16 < a.hK) frag_load(hwf[mh][cc], hw + ((((size_t)mh * (TM / 2)) + cc) * 64 + lane) * 8);
+    float hb[4][4];
+#pragma unroll
+    for (int mh = 0; mh < 4; ++mh)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = mh * 16 + 4 * (lane >> 4) + q;
+        hb[mh][q] = k < a.hK ? a.hb[k] : 0.f;
+      }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int row = row0 + j;
@@ -234,12 +251,17 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
         for (int q = 0; q < 4; ++q) {
           const float t = acc[m][j][q] + bv[m][q];
           v[q] = a.relu ? fmaxf(t, 0.f) : t;
-          Ys[(lane & 15) * YP + co0 + q] = f2t<T>(v[q]);
         }
+        if constexpr (sizeof(T) == 2)
+          *reinterpret_cast<u16x4*>(Ys + (lane & 15) * YP + co0) = f2bf4(v[0], v[1], v[2], v[3]);
+        else
+          *reinterpret_cast<float4*>(Ys + (lane & 15) * YP + co0) = make_float4(v[0], v[1], v[2], v[3]);
         if (a.store_main && inpx)
           store_out<TO>(y + (((size_t)n * a.H + row) * a.W + col) * a.ldy, a.ldy, co0, a.Cout, v);
       }
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       Frag<T> bf[TM / 2];
 #pragma unroll
       for (int cc = 0; cc < TM / 2; ++cc) frag_load(bf[cc], Ys + (lane & 15) * YP + 32 * cc + 8 * (lane >> 4));
@@ -248,20 +270,19 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
         if (mh * 16 >= a.hK) break;
         f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int cc = 0; cc < TM / 2; ++cc) {
-          Frag<T> wf;
-          frag_load(wf, hw + ((((size_t)mh * (TM / 2)) + cc) * 64 + lane) * 8);
-          h = mma(wf, bf[cc], h);
-        }
+        for (int cc = 0; cc < TM / 2; ++cc) h = mma(hwf[mh][cc], bf[cc], h);
         const int k0 = mh * 16 + 4 * (lane >> 4);
         if (inpx && k0 < a.hK) {
-          float v[4];
+          float o[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = h[q] + (k0 + q < a.hK ? a.hb[k0 + q] : 0.f);
-          store_out<TO>(hy + (((size_t)n * a.H + row) * a.W + col) * a.hldy, a.hldy, k0, a.hK, v);
+          for (int q = 0; q < 4; ++q) o[q] = h[q] + hb[mh][q];
+          store_out<TO>(hy + (((size_t)n * a.H + row) * a.W + col) * a.hldy, a.hldy, k0, a.hK, o);
         }
       }
-      __syncthreads();
+      // the next row's re-layout overwrites Ys
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
@@ -510,19 +531,49 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   } else {
     // bf16 store of 4 channels per lane; ReLU on the rounded bits (round-to-nearest-even keeps
     // the sign, so this equals rounding max(v, 0)).  Cout % 16 == 0 and ldy % 4 == 0 (host).
+    // With a.pool, the 2x2 mean of the stored values (rows j, j+1 of this lane; columns of
+    // this lane and its neighbour lane ^ 1), summed in the order of the POOL2 input transform,
+    // goes to the half-resolution tensor; H, W and the tile origins are even.
     uint16_t* y = static_cast<uint16_t*>(a.y);
+    uint16_t* yp = static_cast<uint16_t*>(a.pool);
     const int col = tx0 + (lane & 15);
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int row = ty0 + wave * TN + j;
-      if (row >= a.H || col >= a.W) continue;
-      uint16_t* py = y + (((size_t)n * a.H + row) * a.W + col) * a.ldy + cob * TM * 16 + 4 * (lane >> 4);
+    for (int j0 = 0; j0 < TN; j0 += 2) {
 #pragma unroll
       for (int m = 0; m < TM; ++m) {
-        if ((cob * TM + m) * 16 >= a.Cout) continue;
-        s16x4 h = __builtin_bit_cast(s16x4, f2bf4(acc[m][j][0], acc[m][j][1], acc[m][j][2], acc[m][j][3]));
-        if (a.relu) h = __builtin_elementwise_max(h, s16x4{0, 0, 0, 0});
-        *reinterpret_cast<s16x4*>(py + m * 16) = h;
+        const int co = (cob * TM + m) * 16 + 4 * (lane >> 4);
+        if (co >= a.Cout) continue;
+        s16x4 h[2];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int j = j0 + jj, row = ty0 + wave * TN + j;
+          h[jj] = __builtin_bit_cast(s16x4, f2bf4(acc[m][j][0], acc[m][j][1], acc[m][j][2], acc[m][j][3]));
+          if (a.relu) h[jj] = __builtin_elementwise_max(h[jj], s16x4{0, 0, 0, 0});
+          if (row < a.H && col < a.W)
+            *reinterpret_cast<s16x4*>(y + (((size_t)n * a.H + row) * a.W + col) * a.ldy + co) = h[jj];
+        }
+        if (yp) {
+          // neighbour column's values (all lanes take part in the exchange)
+          s16x4 nb[2];
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            const uint2 u = __builtin_bit_cast(uint2, h[jj]);
+            // DPP quad_perm [1,0,3,2]: lane l reads lane l ^ 1
+            nb[jj] = __builtin_bit_cast(
+                s16x4, make_uint2((uint32_t)__builtin_amdgcn_update_dpp(0, (int)u.x, 0xB1, 0xF, 0xF, true),
+                                  (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u.y, 0xB1, 0xF, 0xF, true)));
+          }
+          const int row = ty0 + wave * TN + j0;
+          if ((lane & 1) == 0 && row < a.H && col < a.W) {
+            float r[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              r[e] = ((bf2f((uint16_t)h[0][e]) + bf2f((uint16_t)nb[0][e])) +
+                      (bf2f((uint16_t)h[1][e]) + bf2f((uint16_t)nb[1][e]))) * 0.25f;
+            *reinterpret_cast<u16x4*>(yp + (((size_t)n * (a.H / 2) + row / 2) * (a.W / 2) + col / 2) * a.Cout + co) =
+                f2bf4(r[0], r[1], r[2], r[3]);
+          }
+        }
       }
     }
   }
@@ -1155,6 +1206,46 @@ int aps_conv2d_bwd_weight(const void* x, const void* x2, int mode, int N, int H,
 }  // extern "C"
 
 extern "C" {
+
+int aps_conv2d_fwd_pool(const void* x, const void* x2, int N, int H, int W, int Cx, int C2,
+                        int mode, const void* packed_w, const float* bias, int Cout, int relu,
+                        int dtype, void* y, void* pooled, void* stream) {
+  if (N < 0 || H < 0 || W < 0 || Cx <= 0 || C2 < 0 || Cout <= 0) return APS_ERR_SHAPE;
+  if (dtype != APS_BF16) return dtype == APS_F32 ? APS_ERR_UNSUPPORTED : APS_ERR_ARG;
+  if (H % 2 || W % 2) return APS_ERR_SHAPE;
+  if (mode == APS_CONV_UP2_CAT) {
+    if (C2 <= 0) return APS_ERR_SHAPE;
+  } else if (mode == APS_CONV_DIRECT || mode == APS_CONV_POOL2) {
+    if (C2 != 0) return APS_ERR_SHAPE;
+  } else {
+    return APS_ERR_ARG;
+  }
+  if (Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2) != 4 || Cout % 16 || Cout <= 16)
+    return APS_ERR_UNSUPPORTED;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!x || !packed_w || !bias || !y || !pooled || (mode == APS_CONV_UP2_CAT && !x2))
+    return APS_ERR_NULL;
+  ConvArgs a{};
+  a.x = x;
+  a.x2 = x2;
+  a.N = N;
+  a.H = H;
+  a.W = W;
+  a.Cx = Cx;
+  a.C2 = C2;
+  a.mode = mode;
+  a.wp = packed_w;
+  a.bias = bias;
+  a.Cout = Cout;
+  a.nchunk = (Cx + C2 + kChunk - 1) / kChunk;
+  a.y = y;
+  a.ldy = Cout;
+  a.relu = relu;
+  a.pool = pooled;
+  if (!launch_conv_lds<false>(a, as_stream(stream))) return APS_ERR_UNSUPPORTED;
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
 
 int aps_conv2d_fwd_head(const void* x, const void* x2, int N, int H, int W, int Cx, int C2,
                         int mode, const void* packed_w, const float* bias, int Cout, int relu,

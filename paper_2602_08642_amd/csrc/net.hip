@@ -77,6 +77,9 @@ size_t aps_kernel_predict_workspace_size(const aps_net* net, int N, int H, int W
   b += align256(px / 4 * c1 * e);        // e1
   b += align256(px / 16 * c2 * e);       // e2
   b += align256(px / 64 * c3 * e);       // e3
+  b += align256(px / 4 * c0 * e);        // pooled e0 (input of enc1a)
+  b += align256(px / 16 * c1 * e);       // pooled e1
+  b += align256(px / 64 * c2 * e);       // pooled e2
   b += align256(px / 16 * c2 * e);       // d2
   b += align256(px / 4 * c1 * e);        // d1
   b += align256(px * c0 * e);            // d0
@@ -113,19 +116,42 @@ int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W
   void* e1 = take(px / 4 * c1 * e);
   void* e2 = take(px / 16 * c2 * e);
   void* e3 = take(px / 64 * c3 * e);
+  void* p0 = take(px / 4 * c0 * e);
+  void* p1 = take(px / 16 * c1 * e);
+  void* p2 = take(px / 64 * c2 * e);
   void* d2 = take(px / 16 * c2 * e);
   void* d1 = take(px / 4 * c1 * e);
   void* d0 = take(px * c0 * e);
   void* t = p;
   const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
-  // encoder
+  // encoder: the second conv of each level also writes its 2x2-pooled output when the kernel
+  // supports it, and the next level reads that directly; otherwise the next level pools on load
+  auto down = [&](int li, const void* in, int h, int w, int cin, void* skip, int cskip, void* pooled,
+                  const void*& next_in, int& next_mode) -> int {
+    const aps_conv_layer& A = L[li];
+    if (!A.w || !A.b) return APS_ERR_NULL;
+    if (A.cin != cin || A.cout != cskip) return APS_ERR_SHAPE;
+    const int r = aps_conv2d_fwd_pool(in, nullptr, N, h, w, cin, 0, APS_CONV_DIRECT, A.w, A.b,
+                                      A.cout, A.relu, dt, skip, pooled, stream);
+    if (r == APS_OK) {
+      next_in = pooled;
+      next_mode = APS_CONV_DIRECT;
+      return APS_OK;
+    }
+    if (r != APS_ERR_UNSUPPORTED) return r;
+    next_in = skip;
+    next_mode = APS_CONV_POOL2;
+    return conv(A, in, nullptr, N, h, w, cin, 0, APS_CONV_DIRECT, dt, skip, cskip, dt, stream);
+  };
+  const void* nin = nullptr;
+  int nmode = APS_CONV_DIRECT;
   APS_TRY(conv(L[0], feat, nullptr, N, H, W, C, 0, APS_CONV_DIRECT, dt, t, L[0].cout, dt, stream));
-  APS_TRY(conv(L[1], t, nullptr, N, H, W, L[0].cout, 0, APS_CONV_DIRECT, dt, e0, c0, dt, stream));
-  APS_TRY(conv(L[2], e0, nullptr, N, H1, W1, c0, 0, APS_CONV_POOL2, dt, t, L[2].cout, dt, stream));
-  APS_TRY(conv(L[3], t, nullptr, N, H1, W1, L[2].cout, 0, APS_CONV_DIRECT, dt, e1, c1, dt, stream));
-  APS_TRY(conv(L[4], e1, nullptr, N, H2, W2, c1, 0, APS_CONV_POOL2, dt, t, L[4].cout, dt, stream));
-  APS_TRY(conv(L[5], t, nullptr, N, H2, W2, L[4].cout, 0, APS_CONV_DIRECT, dt, e2, c2, dt, stream));
-  APS_TRY(conv(L[6], e2, nullptr, N, H3, W3, c2, 0, APS_CONV_POOL2, dt, t, L[6].cout, dt, stream));
+  APS_TRY(down(1, t, H, W, L[0].cout, e0, c0, p0, nin, nmode));
+  APS_TRY(conv(L[2], nin, nullptr, N, H1, W1, c0, 0, nmode, dt, t, L[2].cout, dt, stream));
+  APS_TRY(down(3, t, H1, W1, L[2].cout, e1, c1, p1, nin, nmode));
+  APS_TRY(conv(L[4], nin, nullptr, N, H2, W2, c1, 0, nmode, dt, t, L[4].cout, dt, stream));
+  APS_TRY(down(5, t, H2, W2, L[4].cout, e2, c2, p2, nin, nmode));
+  APS_TRY(conv(L[6], nin, nullptr, N, H3, W3, c2, 0, nmode, dt, t, L[6].cout, dt, stream));
   APS_TRY(conv(L[7], t, nullptr, N, H3, W3, L[6].cout, 0, APS_CONV_DIRECT, dt, e3, c3, dt, stream));
   // decoder: concat [nearest-2x(deeper), skip]
   APS_TRY(conv(L[8], e3, e2, N, H2, W2, c3, c2, APS_CONV_UP2_CAT, dt, t, L[8].cout, dt, stream));
