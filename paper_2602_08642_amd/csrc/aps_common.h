@@ -111,4 +111,11 @@ template <> struct Ld<uint16_t> {
   static __device__ inline float get(const uint16_t* p, size_t i) { return bf2f(p[i]); }
 };
 
+// Fused sampler CNN (conv.hip): x [N,H,W,C] (dtype), three 3x3 layers Cin->16 (ReLU) ->16 (ReLU)
+// ->1 with packed weights w0..w2 and biases b0..b2, z [N,H,W] float32.  Returns an aps_status;
+// APS_ERR_UNSUPPORTED when the shapes are not covered (the caller then runs the layers one by one).
+int sampler_cnn(const void* x, int N, int H, int W, int C, int Cin, const void* w0, const float* b0,
+                const void* w1, const float* b1, const void* w2, const float* b2, int dtype, float* z,
+                hipStream_t st);
+
 }  // namespace aps

@@ -623,6 +623,143 @@ bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
   }
 }
 
+// ---- fused sampler CNN ----------------------------------------------------------------------
+// The three 3x3 'same' convolutions of the sampler (Cin -> 16, ReLU; 16 -> 16, ReLU; 16 -> 1)
+// in one kernel.  A block stages its 22x22 input tile (16x16 outputs + 3-px halo) once; the two
+// intermediates (20x20 and 18x18 pixels x 16 channels) stay in LDS, zero outside the image and
+// rounded to T, as the layer-by-layer path stores them.  K enumerates (tap, 8-channel group)
+// pairs as in k_conv's CG < 4 layout (same packed weights); MFMA n-tiles are 16 consecutive
+// pixels of a layer's output grid, so B fragments are gathered per lane.
+struct SamplerArgs {
+  const void* x;
+  int N, H, W, C, ntx;
+  const void* w[3];  // packed weights of the three layers
+  const float* b[3];
+  float* z;
+};
+
+// One hidden layer (16 outputs, ReLU) on MFMA: output grid WOUT x WOUT at image (oy, ox),
+// input grid WIN x WIN in LDS (pixel stride psin), output to Y (pixel stride PSO).
+template <typename T, int CG, int WIN, int WOUT, int PSO>
+__device__ inline void sampler_hidden(const T* Xin, int psin, T* Y, const T* wp, const float* bias,
+                                      int H, int W, int oy, int ox, int lane, int wave) {
+  constexpr int NPAIR = 9 * CG, STEPS = (NPAIR + 3) / 4, NPX = WOUT * WOUT;
+  Frag<T> wf[STEPS];
+  int off[STEPS];  // this lane's LDS offset of its (tap, group) pair at each K step
+#pragma unroll
+  for (int s = 0; s < STEPS; ++s) {
+    frag_load(wf[s], wp + ((size_t)s * 64 + lane) * 8);
+    const int p = 4 * s + (lane >> 4);
+    const int tap = p < NPAIR ? p / CG : 0, g = p < NPAIR ? p % CG : 0;  // padded pairs: zero weights
+    off[s] = ((tap / 3) * WIN + tap % 3) * psin + g * 8;
+  }
+  const f32x4 b = *reinterpret_cast<const f32x4*>(bias + 4 * (lane >> 4));  // added after the sum
+  for (int tile = wave; tile * 16 < NPX; tile += 4) {
+    const int pix = tile * 16 + (lane & 15);
+    const bool valid = pix < NPX;
+    const int pp = valid ? pix : 0, r = pp / WOUT, c = pp - r * WOUT;
+    const T* base = Xin + (r * WIN + c) * psin;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+      Frag<T> bf;
+      frag_load(bf, base + off[s]);
+      acc = mma(wf[s], bf, acc);
+    }
+    if (valid) {
+      const int iy = oy + r, ix = ox + c;
+      const bool inside = iy >= 0 && iy < H && ix >= 0 && ix < W;
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = inside ? fmaxf(acc[q] + b[q], 0.f) : 0.f;
+      T* d = Y + pix * PSO + 4 * (lane >> 4);
+      if constexpr (sizeof(T) == 2) *reinterpret_cast<u16x4*>(d) = f2bf4(v[0], v[1], v[2], v[3]);
+      else *reinterpret_cast<float4*>(d) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// The 16 -> 1 output layer on MFMA over the 18x18 map: 16 output pixels per tile.
+template <typename T>
+__device__ inline void sampler_out_mfma(const T* Xin, int psin, const T* wp, float bias, float* z, int H,
+                                        int W, int oy, int ox, int n, int lane, int wave) {
+  constexpr int STEPS = 5;
+  Frag<T> wf[STEPS];
+  int off[STEPS];
+#pragma unroll
+  for (int s = 0; s < STEPS; ++s) {
+    frag_load(wf[s], wp + ((size_t)s * 64 + lane) * 8);
+    const int p = 4 * s + (lane >> 4);
+    const int tap = p < 18 ? p / 2 : 0, g = p < 18 ? p % 2 : 0;
+    off[s] = ((tap / 3) * 18 + tap % 3) * psin + g * 8;
+  }
+  for (int tile = wave; tile < 16; tile += 4) {
+    const int r = tile, c = lane & 15;  // 16x16 outputs: one row per tile
+    const T* base = Xin + (r * 18 + c) * psin;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+      Frag<T> bf;
+      frag_load(bf, base + off[s]);
+      acc = mma(wf[s], bf, acc);
+    }
+    const int iy = oy + r, ix = ox + c;
+    if (lane < 16 && iy < H && ix < W) z[((size_t)n * H + iy) * W + ix] = acc[0] + bias;
+  }
+}
+
+template <typename T, int CG0>
+__global__ __launch_bounds__(256) void k_sampler_cnn(SamplerArgs a) {
+  constexpr int PS0 = CG0 * 8 + (sizeof(T) == 2 ? (CG0 == 2 ? 8 : 0) : 4);
+  constexpr int PS = sizeof(T) == 2 ? 24 : 20;  // 16 channels + pad
+  constexpr int X0N = 22 * 22 * PS0, H2N = 18 * 18 * PS;
+  __shared__ __attribute__((aligned(16))) T X0[X0N > H2N ? X0N : H2N];  // the 18x18 map reuses it
+  __shared__ __attribute__((aligned(16))) T H1[20 * 20 * PS];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tx0 = (blockIdx.x % a.ntx) * 16, ty0 = (blockIdx.x / a.ntx) * 16, n = blockIdx.z;
+  const T* x = static_cast<const T*>(a.x);
+  for (int it = tid; it < 22 * 22 * CG0; it += 256) {
+    const int g = it % CG0, p = it / CG0, r = p / 22, c = p - r * 22;
+    const int iy = ty0 - 3 + r, ix = tx0 - 3 + c;
+    T* d = X0 + p * PS0 + g * 8;
+    if (iy >= 0 && iy < a.H && ix >= 0 && ix < a.W)
+      copy8(d, x + (((size_t)n * a.H + iy) * a.W + ix) * a.C + g * 8);
+    else
+      zero8(d);
+  }
+  __syncthreads();
+  sampler_hidden<T, CG0, 22, 20, PS>(X0, PS0, H1, static_cast<const T*>(a.w[0]), a.b[0], a.H, a.W,
+                                     ty0 - 2, tx0 - 2, lane, wave);
+  __syncthreads();
+  sampler_hidden<T, 2, 20, 18, PS>(H1, PS, X0, static_cast<const T*>(a.w[1]), a.b[1], a.H, a.W,
+                                   ty0 - 1, tx0 - 1, lane, wave);
+  __syncthreads();
+  if constexpr (sizeof(T) == 2) {
+    // 16 -> 1 output layer on MFMA (row 0 of the 16-row tile is the output channel)
+    sampler_out_mfma<T>(X0, PS, static_cast<const T*>(a.w[2]), a.b[2][0], a.z, a.H, a.W, ty0, tx0, n, lane, wave);
+  } else {
+    // fp32: on the vector ALU, one output pixel per thread, since an fp32 MFMA tile would spend
+    // 15 of its 16 rows on padding.  Weights are read from the packed buffer (output channel 0:
+    // lane 16 (p % 4) of step p / 4 for pair p = 2 tap + ci / 8).
+    const int r = tid >> 4, c = tid & 15;
+    const float* wp2 = static_cast<const float*>(a.w[2]);
+    float acc = 0.f;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const float* px = reinterpret_cast<const float*>(X0) + ((r + tap / 3) * 18 + c + tap % 3) * PS;
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int pr = 2 * tap + g;
+        const float* wv = wp2 + ((pr / 4) * 64 + 16 * (pr % 4)) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc = fmaf(wv[e], px[g * 8 + e], acc);
+      }
+    }
+    const int iy = ty0 + r, ix = tx0 + c;
+    if (iy < a.H && ix < a.W) a.z[((size_t)n * a.H + iy) * a.W + ix] = acc + a.b[2][0];
+  }
+}
+
 // ---- weight packing: OHWI fp32 -> fragment order --------------------------------------
 // packed[(((ct * KS*KS + tap) * nchunk + c) * 64 + lane) * 8 + e] =
 //     w[co = 16 ct + lane % 16][tap][ci = 32 c + 8 (lane / 16) + e]   (0 outside)
@@ -1300,3 +1437,38 @@ int aps_conv2d_fwd_head(const void* x, const void* x2, int N, int H, int W, int 
 }
 
 }  // extern "C"
+
+namespace aps {
+int sampler_cnn(const void* x, int N, int H, int W, int C, int Cin, const void* w0, const float* b0,
+                const void* w1, const float* b1, const void* w2, const float* b2, int dtype, float* z,
+                hipStream_t st) {
+  if (Cin > 16 || C % 8 || C < Cin) return APS_ERR_UNSUPPORTED;
+  SamplerArgs a{};
+  a.x = x;
+  a.N = N;
+  a.H = H;
+  a.W = W;
+  a.C = C;
+  a.ntx = (W + 15) / 16;
+  a.w[0] = w0;
+  a.w[1] = w1;
+  a.w[2] = w2;
+  a.b[0] = b0;
+  a.b[1] = b1;
+  a.b[2] = b2;
+  a.z = z;
+  dim3 grid(a.ntx * ((H + 15) / 16), 1, N);
+  const bool cg1 = Cin <= 8;
+  if (dtype == APS_BF16) {
+    if (cg1) k_sampler_cnn<uint16_t, 1><<<grid, 256, 0, st>>>(a);
+    else k_sampler_cnn<uint16_t, 2><<<grid, 256, 0, st>>>(a);
+  } else if (dtype == APS_F32) {
+    if (cg1) k_sampler_cnn<float, 1><<<grid, 256, 0, st>>>(a);
+    else k_sampler_cnn<float, 2><<<grid, 256, 0, st>>>(a);
+  } else {
+    return APS_ERR_UNSUPPORTED;
+  }
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+}  // namespace aps

@@ -60,9 +60,19 @@ int aps_density_predict(const aps_net* net, const void* feat, int N, int H, int 
   float* z = reinterpret_cast<float*>(p);
   p += align256((size_t)N * H * W * 4);
   if (z_out) z = z_out;
-  APS_TRY(conv(L[0], feat, nullptr, N, H, W, C, 0, APS_CONV_DIRECT, dt, t0, width, dt, stream));
-  APS_TRY(conv(L[1], t0, nullptr, N, H, W, width, 0, APS_CONV_DIRECT, dt, t1, L[1].cout, dt, stream));
-  APS_TRY(conv(L[2], t1, nullptr, N, H, W, L[1].cout, 0, APS_CONV_DIRECT, dt, z, 1, APS_F32, stream));
+  // the three layers in one kernel when they have the configured shape (16-channel hidden
+  // layers with ReLU, linear 1-channel output, 3x3 kernels)
+  int fused = APS_ERR_UNSUPPORTED;
+  if (L[0].w && L[0].b && L[1].w && L[1].b && L[2].w && L[2].b && width == 16 && L[1].cout == 16 &&
+      L[0].ksize == 3 && L[1].ksize == 3 && L[2].ksize == 3 && L[0].relu && L[1].relu && !L[2].relu)
+    fused = sampler_cnn(feat, N, H, W, C, C, L[0].w, L[0].b, L[1].w, L[1].b, L[2].w, L[2].b, dt, z,
+                        as_stream(stream));
+  if (fused != APS_OK) {
+    if (fused != APS_ERR_UNSUPPORTED) return fused;
+    APS_TRY(conv(L[0], feat, nullptr, N, H, W, C, 0, APS_CONV_DIRECT, dt, t0, width, dt, stream));
+    APS_TRY(conv(L[1], t0, nullptr, N, H, W, width, 0, APS_CONV_DIRECT, dt, t1, L[1].cout, dt, stream));
+    APS_TRY(conv(L[2], t1, nullptr, N, H, W, L[1].cout, 0, APS_CONV_DIRECT, dt, z, 1, APS_F32, stream));
+  }
   return aps_normalize_density(z, N, H, W, budget_spp, uniform_frac, s_out, p,
                                aps_normalize_workspace_size(N, H, W), dev_status, stream);
 }

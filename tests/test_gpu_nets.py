@@ -69,19 +69,46 @@ def test_fused_head_bit_identical(ops, dtype, cout, K):
     assert torch.equal(ymain, y)
 
 
-def test_sampler_cnn_matches_oracle(ops):
-    spec = procgen.density_cnn_spec(16)
+@pytest.mark.parametrize("cin", [8, 16])
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.bfloat16, 2e-2)])
+def test_sampler_cnn_matches_oracle(ops, cin, dtype, tol):
+    spec = procgen.density_cnn_spec(cin)
     w = procgen.init_weights(spec, 5)
-    net = ops.Net(spec, w, torch.float32, DEV)
-    g = torch.Generator().manual_seed(2)
-    x = torch.rand(2, 40, 56, 16, generator=g)
-    z, s = ops.density_predict(net, x.to(DEV), 0.25)
-    layers = [(torch.tensor(w[l["name"]][0], dtype=torch.float64), torch.tensor(w[l["name"]][1], dtype=torch.float64),
+    net = ops.Net(spec, w, dtype, DEV)
+    g = torch.Generator().manual_seed(2 + cin)
+    x = torch.rand(2, 40, 56, cin, generator=g)
+    z, s = ops.density_predict(net, x.to(DEV).to(dtype), 0.25)
+    layers = [(torch.tensor(w[l["name"]][0]).to(dtype).double(), torch.tensor(w[l["name"]][1], dtype=torch.float64),
                l["relu"]) for l in spec]
-    zr = odens.cnn_forward(x.double(), layers)[..., 0]
-    assert rel_norm(z.cpu(), zr) < 1e-5
+    zr = odens.cnn_forward(x.to(dtype).double(), layers)[..., 0]
+    assert rel_norm(z.cpu(), zr) < tol
     sr = odens.normalise(z.double().cpu(), 0.25)
     assert rel_norm(s.cpu(), sr) < 1e-6
+
+
+@pytest.mark.parametrize("cin", [8, 16])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("H,W", [(40, 56), (23, 37), (1, 5)])
+def test_fused_sampler_equals_layer_by_layer(ops, cin, dtype, H, W):
+    """The one-kernel sampler CNN gives the layer-by-layer result, including ragged tiles and
+    one-row images: bit for bit in bf16 (same K order, same rounding of the stored
+    intermediates); in fp32 the 16 -> 1 output layer sums on the vector ALU in another order."""
+    spec = procgen.density_cnn_spec(cin)
+    w = procgen.init_weights(spec, 9)
+    net = ops.Net(spec, w, dtype, DEV)
+    g = torch.Generator().manual_seed(H * W + cin)
+    x = (torch.rand(3, H, W, cin, generator=g) * 2 - 0.5).to(DEV).to(dtype)
+    z, _ = ops.density_predict(net, x, 0.25)
+    h = x
+    for l in spec[:2]:
+        ls, pk, b = net.layer(l["name"])
+        h = ops.conv2d(h, ls, pk, b)
+    ls, pk, b = net.layer(spec[2]["name"])
+    zr = ops.conv2d(h, ls, pk, b, out_dtype=torch.float32)[..., 0]
+    if dtype == torch.bfloat16:
+        assert torch.equal(z, zr)
+    else:
+        assert torch.allclose(z, zr, rtol=1e-5, atol=1e-5 * float(zr.abs().max()))
 
 
 @pytest.mark.parametrize("cin,cout,H,W", [(32, 32, 40, 72), (64, 64, 24, 48), (128, 128, 16, 32),
