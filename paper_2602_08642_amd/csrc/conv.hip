@@ -35,7 +35,22 @@ struct ConvArgs {
   int hldy, store_main;
   // optional 2x2 average pool of the (bf16-rounded) output, [N, H/2, W/2, Cout] (k_conv_lds)
   void* pool;
+  int ntiles, nco;  // pixel tiles per image, output-channel blocks (block order: xcd_tile)
 };
+
+// Blocks are dispatched round-robin over the 8 XCDs (block id % 8), each with its own L2.  XCD x
+// takes the contiguous tile range [x T8, (x+1) T8) and, per tile, all channel blocks back to back,
+// so the halo rows shared by neighbouring tiles and the input tile shared by a tile's channel
+// blocks are re-read from that XCD's L2 rather than from HBM.  grid.x = 8 T8 nco; blocks past the
+// last tile exit.
+struct TileId {
+  int tile, cob;
+};
+__device__ inline TileId xcd_tile(int id, int ntiles, int nco) {
+  const int t8 = (ntiles + 7) / 8, xcd = id & 7, k = id >> 3;
+  return TileId{xcd * t8 + k / nco, k % nco};
+}
+inline int xcd_grid(int ntiles, int nco) { return 8 * ((ntiles + 7) / 8) * nco; }
 
 // ---- 8-element vectors of the storage type ---------------------------------------------
 struct V8f {
@@ -300,8 +315,10 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   __shared__ __attribute__((aligned(16))) T Xs[SH * SW * PS];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int tx0 = (blockIdx.x % a.ntx) * TWp, ty0 = (blockIdx.x / a.ntx) * TH;
-  const int cob = blockIdx.y, n = blockIdx.z;
+  const TileId tid_ = xcd_tile(blockIdx.x, a.ntiles, a.nco);
+  if (tid_.tile >= a.ntiles) return;
+  const int tx0 = (tid_.tile % a.ntx) * TWp, ty0 = (tid_.tile / a.ntx) * TH;
+  const int cob = tid_.cob, n = blockIdx.z;
   const T* wp = static_cast<const T*>(a.wp);
 
   f32x4 acc[TM][TN];
@@ -393,8 +410,10 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t As[NAV * 8];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int tx0 = (blockIdx.x % a.ntx) * 16, ty0 = (blockIdx.x / a.ntx) * ROWS;
-  const int cob = blockIdx.y, n = blockIdx.z;
+  const TileId tid_ = xcd_tile(blockIdx.x, a.ntiles, a.nco);
+  if (tid_.tile >= a.ntiles) return;
+  const int tx0 = (tid_.tile % a.ntx) * 16, ty0 = (tid_.tile / a.ntx) * ROWS;
+  const int cob = tid_.cob, n = blockIdx.z;
   const uint16_t* x = static_cast<const uint16_t*>(a.x);
   const uint16_t* x2 = static_cast<const uint16_t*>(a.x2);
   const uint16_t* wp = static_cast<const uint16_t*>(a.wp);
@@ -588,7 +607,9 @@ void launch_conv_lds_m(const ConvArgs& a, hipStream_t st) {
   b.ntx = (a.W + 15) / 16;
   const bool small = (size_t)a.N * a.H * a.W < 64 * 64 * 8;
   const int rows = small ? 8 : 16;
-  dim3 grid(b.ntx * ((a.H + rows - 1) / rows), a.Cout <= 32 ? 1 : (a.Cout + 63) / 64, a.N);
+  b.ntiles = b.ntx * ((a.H + rows - 1) / rows);
+  b.nco = a.Cout <= 32 ? 1 : (a.Cout + 63) / 64;
+  dim3 grid(xcd_grid(b.ntiles, b.nco), 1, a.N);
   if (a.Cout <= 32) {
     if (small) k_conv_lds<MODE, 2, 2, HEAD><<<grid, 256, 0, st>>>(b);
     else k_conv_lds<MODE, 2, 4, HEAD><<<grid, 256, 0, st>>>(b);
@@ -819,8 +840,9 @@ void launch_conv(const ConvArgs& a, hipStream_t st) {
   const int ntx = (a.W + 15) / 16, nty = (a.H + TH - 1) / TH;
   ConvArgs b = a;
   b.ntx = ntx;
-  const int nco = (a.Cout + 16 * TM - 1) / (16 * TM);
-  dim3 grid(ntx * nty, nco, a.N);
+  b.ntiles = ntx * nty;
+  b.nco = (a.Cout + 16 * TM - 1) / (16 * TM);
+  dim3 grid(xcd_grid(b.ntiles, b.nco), 1, a.N);
   k_conv<T, TO, KS, TM, TN, CG><<<grid, 256, 0, st>>>(b);
 }
 
@@ -834,7 +856,9 @@ void launch_conv_head(const ConvArgs& a, hipStream_t st) {
   const int TN = big ? 4 : 2, TH = 4 * TN;
   ConvArgs b = a;
   b.ntx = (a.W + 15) / 16;
-  dim3 grid(b.ntx * ((a.H + TH - 1) / TH), 1, a.N);
+  b.ntiles = b.ntx * ((a.H + TH - 1) / TH);
+  b.nco = 1;
+  dim3 grid(xcd_grid(b.ntiles, 1), 1, a.N);
   if (big) k_conv<T, T, 3, TM, 4, 4, true><<<grid, 256, 0, st>>>(b);
   else k_conv<T, T, 3, TM, 2, 4, true><<<grid, 256, 0, st>>>(b);
 }
