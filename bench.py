@@ -97,8 +97,10 @@ def cpu_baseline(cfg, dw, kw, rows: int):
     assert torch.isfinite(out).all()
     return dict(value=round(H * W / dt / 1e6, 5), unit="Mpixel/s", cores=torch.get_num_threads(),
                 kind="oracle", seconds=round(dt, 3),
-                sample=f"one {W}x{H} band of the {cfg.W}x{cfg.H} frame, full path (sampler CNN, "
-                       f"normalisation, mask, scatter, pyramid, U-Net, gathering pyramid) in FP64")
+                sample=(f"one {W}x{H} band of the {cfg.W}x{cfg.H} frame" if H < cfg.H else
+                        f"one whole {W}x{H} frame") +
+                       ", full path (sampler CNN, normalisation, mask, scatter, pyramid, U-Net, "
+                       "gathering pyramid) in FP64")
 
 
 def bench_config(name, steps, warmup, dev, seed=2602):
@@ -281,7 +283,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--also", default="c3,c5", help="other configurations timed beside (or '')")
-    ap.add_argument("--cpu-rows", type=int, default=64)
+    ap.add_argument("--cpu-rows", type=int, default=0,
+                    help="rows of the frame the CPU oracle processes (0: the whole frame)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -346,7 +349,7 @@ def main():
         if q is not None:
             res["learned_vs_uniform"] = q
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(cfg, r["dw"], r["kw"], args.cpu_rows)
+        res["cpu_baseline"] = cpu_baseline(cfg, r["dw"], r["kw"], args.cpu_rows or cfg.H)
     print(json.dumps(res))
 
 
