@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   float sum = 0.f;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    z[k] = expf(z[k] - m);
+    z[k] = softmax_exp(z[k] - m);
     sum += z[k];
   }
   float ax = 0.f, ay = 0.f, az = 0.f;

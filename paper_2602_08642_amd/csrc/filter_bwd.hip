@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_level_bwd(BwdArgs b) {
   float sum = 0.f;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    z[k] = expf(z[k] - m);
+    z[k] = softmax_exp(z[k] - m);
     sum += z[k];
   }
   const float inv = 1.f / sum;

@@ -86,6 +86,10 @@ __device__ inline float4 warp_at(const float4* __restrict__ prev, const float2* 
                      t.gy * (t.gx * a.z + t.fx * b.z) + t.fy * (t.gx * c.z + t.fx * d.z), 0.f);
 }
 
+// e^x for x <= 0 (softmax numerators after the max subtraction) as one hardware exp2: the
+// relative error is about (|x| + 1) 2^-23, below 1e-5 for the logit spreads that carry weight.
+__device__ inline float softmax_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
 // Tile geometry of one level kernel instantiation.
 template <int KD, int KU, int KT, bool HU, bool HT>
 struct Geo {
