@@ -446,49 +446,63 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   const uint32_t wo = (uint32_t)((((size_t)cob * TM * 9 + wave) * a.nchunk) * 512 + lane * 8);
   const uint32_t wstep = (uint32_t)(4 * a.nchunk * 512);
 
+  // Global loads of the next chunk are issued unconditionally (out-of-range lanes read a valid
+  // dummy address) so that no branch join forces the compiler to wait for them before the
+  // current chunk's MFMAs; the zero fill of halo pixels and channels beyond Cin is applied when
+  // the registers are written to LDS.  The pooled and masked transforms combine several loads
+  // and are evaluated at fetch time.
   u16x8 px[NXT], pa[NAT];
+  uint32_t okbits = 0;
   auto fetch = [&](int c) {
     const int cb = c * kChunk;
     const bool in_ch = cb + g8 < Cin;
+    okbits = 0;
 #pragma unroll
     for (int k = 0; k < NXT; ++k) {
-      u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      if (xo[k] != kNoPixel && in_ch) {
-        if constexpr (MODE == APS_CONV_DIRECT) {
-          v = *reinterpret_cast<const u16x8*>(x + (xo[k] + cb));
-        } else if constexpr (MODE == kModeReluMask) {
-          // x = dLoss/dy, x2 = the layer's post-ReLU output: dy where y > 0
-          const u16x8 gr = *reinterpret_cast<const u16x8*>(x + (xo[k] + cb));
-          const u16x8 yv = *reinterpret_cast<const u16x8*>(x2 + (xo[k] + cb));
+      const bool ok = xo[k] != kNoPixel && in_ch;
+      okbits |= (uint32_t)ok << k;
+      if constexpr (MODE == APS_CONV_DIRECT) {
+        px[k] = *reinterpret_cast<const u16x8*>(x + (ok ? xo[k] + cb : 0u));
+      } else if constexpr (MODE == APS_CONV_UP2_CAT) {
+        // channels [0, Cx) from the coarse tensor, then the skip tensor
+        const uint16_t* src = cb + g8 < a.Cx ? x + (xo[k] + cb) : x2 + (so[k] + (cb - a.Cx));
+        px[k] = *reinterpret_cast<const u16x8*>(ok ? src : x);
+      } else {
+        u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (ok) {
+          if constexpr (MODE == kModeReluMask) {
+            // x = dLoss/dy, x2 = the layer's post-ReLU output: dy where y > 0
+            const u16x8 gr = *reinterpret_cast<const u16x8*>(x + (xo[k] + cb));
+            const u16x8 yv = *reinterpret_cast<const u16x8*>(x2 + (xo[k] + cb));
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = bf_pos(yv[e]) ? gr[e] : (uint16_t)0;
-        } else if constexpr (MODE == APS_CONV_POOL2) {
-          const uint32_t rs = (uint32_t)(2 * a.W * a.Cx);
-          const uint32_t o = xo[k] + cb;
-          const V8f q0 = load8(x + o), q1 = load8(x + (o + a.Cx)), q2 = load8(x + (o + rs)),
-                    q3 = load8(x + (o + rs + a.Cx));
-          float r[8];
+            for (int e = 0; e < 8; ++e) v[e] = bf_pos(yv[e]) ? gr[e] : (uint16_t)0;
+          } else {  // APS_CONV_POOL2
+            const uint32_t rs = (uint32_t)(2 * a.W * a.Cx);
+            const uint32_t o = xo[k] + cb;
+            const V8f q0 = load8(x + o), q1 = load8(x + (o + a.Cx)), q2 = load8(x + (o + rs)),
+                      q3 = load8(x + (o + rs + a.Cx));
+            float r[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) r[e] = ((q0.v[e] + q1.v[e]) + (q2.v[e] + q3.v[e])) * 0.25f;
-          const u16x4 lo = f2bf4(r[0], r[1], r[2], r[3]), hi = f2bf4(r[4], r[5], r[6], r[7]);
-          v = u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-        } else {  // APS_CONV_UP2_CAT: channels [0, Cx) from the coarse tensor, then the skip
-          if (cb + g8 < a.Cx) v = *reinterpret_cast<const u16x8*>(x + (xo[k] + cb));
-          else v = *reinterpret_cast<const u16x8*>(x2 + (so[k] + (cb - a.Cx)));
+            for (int e = 0; e < 8; ++e) r[e] = ((q0.v[e] + q1.v[e]) + (q2.v[e] + q3.v[e])) * 0.25f;
+            const u16x4 lo = f2bf4(r[0], r[1], r[2], r[3]), hi = f2bf4(r[4], r[5], r[6], r[7]);
+            v = u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+          }
         }
+        px[k] = v;
       }
-      px[k] = v;
     }
 #pragma unroll
     for (int k = 0; k < NAT; ++k)
-      if (tid + 256 * k < NAV)
-        pa[k] = *reinterpret_cast<const u16x8*>(wp + (wo + k * wstep + c * 512));
+      pa[k] = *reinterpret_cast<const u16x8*>(wp + ((tid + 256 * k < NAV ? wo + k * wstep : wo) + c * 512));
   };
   auto put = [&]() {
 #pragma unroll
     for (int k = 0; k < NXT; ++k) {
       const int p = (tid >> 2) + 64 * k;
-      if (p < SH * SW) *reinterpret_cast<u16x8*>(Xs + p * PS + g8) = px[k];
+      if (p < SH * SW) {
+        const u16x8 v = (okbits >> k) & 1u ? px[k] : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        *reinterpret_cast<u16x8*>(Xs + p * PS + g8) = v;
+      }
     }
 #pragma unroll
     for (int k = 0; k < NAT; ++k) {
