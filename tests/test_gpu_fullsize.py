@@ -1,0 +1,82 @@
+"""Parity at the benchmark's full sizes, in the launch configurations bench.py times: the 1080p
+U-Net (bf16 as in C3, fp32 as in C2), the fused sampler CNN at 1080p and the C3 gathering pyramid
+(bf16 logits, temporal term), each against the FP64 oracle over the whole frame."""
+import numpy as np
+import pytest
+import torch
+
+import procgen
+from oracle import density as odens
+from oracle import filt as ofilt
+from oracle import unet as ounet
+from tests._tol import assert_mag_close, rel_norm
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+H, W = 1080, 1920
+
+
+@pytest.fixture(scope="module")
+def ops():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2602_08642_amd import ops as o
+    return o
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.bfloat16, 2e-2), (torch.float32, 1e-5)])
+def test_unet_1080p_matches_oracle(ops, dtype, tol):
+    heads = [43, 34, 25] if dtype == torch.bfloat16 else [34, 34, 25]
+    spec = procgen.unet_spec(16, heads)
+    w = procgen.init_weights(spec, 21)
+    net = ops.Net(spec, w, dtype, DEV)
+    x = torch.rand(1, H, W, 16, generator=torch.Generator().manual_seed(4))
+    x[..., 15] = 0
+    logits = ops.kernel_predict(net, x.to(DEV).to(dtype), heads, dtype)
+    wq = {k: (torch.tensor(a).to(dtype).double(), torch.tensor(b).double()) for k, (a, b) in w.items()}
+    ref = ounet.unet_forward(x.to(dtype).double(), wq, len(heads))
+    for l, K in enumerate(heads):
+        e = rel_norm(logits[l][..., :K].float().cpu(), ref[l])
+        assert e < tol, (l, e)
+    del ref
+
+
+@pytest.mark.parametrize("cin,dtype,tol", [(16, torch.bfloat16, 2e-2), (8, torch.float32, 1e-5)])
+def test_sampler_1080p_matches_oracle(ops, cin, dtype, tol):
+    spec = procgen.density_cnn_spec(cin)
+    w = procgen.init_weights(spec, 22)
+    net = ops.Net(spec, w, dtype, DEV)
+    x = torch.rand(1, H, W, cin, generator=torch.Generator().manual_seed(5))
+    z, s = ops.density_predict(net, x.to(DEV).to(dtype), 0.25)
+    layers = [(torch.tensor(w[l["name"]][0]).to(dtype).double(), torch.tensor(w[l["name"]][1], dtype=torch.float64),
+               l["relu"]) for l in spec]
+    zr = odens.cnn_forward(x.to(dtype).double(), layers)[..., 0]
+    assert rel_norm(z.cpu(), zr) < tol
+    sr = odens.normalise(z.double().cpu(), 0.25)
+    assert rel_norm(s.cpu(), sr) < 1e-6
+
+
+def test_denoise_pyramid_1080p_c3(ops):
+    """C3 reconstruction: 3 levels, kd 5x5, ku 3x3, kt 3x3, bf16 logits, warped history."""
+    levels, KD, KU, KT = 3, 5, 3, 3
+    g = torch.Generator().manual_seed(23)
+    Ls = [torch.randn(1, H >> l, W >> l, 4, generator=g) * 2.0 for l in range(levels)]
+    for t in Ls:
+        t[..., 3] = 0
+    Ks = procgen.kernel_channels(levels, KD, KU, KT, True)
+    logits = []
+    for l in range(levels):
+        ks = ops.round_kstride(Ks[l], torch.bfloat16)
+        z = torch.randn(1, H >> l, W >> l, ks, generator=g) * 2.0
+        z[..., Ks[l]:] = 0.0
+        logits.append(z.to(torch.bfloat16))
+    prev = torch.randn(1, H, W, 4, generator=g)
+    prev[..., 3] = 0
+    mv = torch.rand(1, H, W, 2, generator=g) * 24 - 12
+    out = ops.denoise_pyramid([t.to(DEV) for t in Ls], [t.to(DEV) for t in logits], KD, KU, KT,
+                              prev.to(DEV), mv.to(DEV))
+    L64 = [t.double() for t in Ls]
+    z64 = [t.double() for t in logits]
+    ref = ofilt.denoise_pyramid(L64, z64, KD, KU, KT, prev.double(), mv.double())[0]
+    mag = ofilt.denoise_magnitude(L64, z64, KD, KU, KT, prev.double(), mv.double())[0]
+    assert_mag_close(out[..., :3], ref[..., :3], mag[..., :3], 1e-5, what="1080p c3")
+    assert torch.all(out[..., 3] == 0)
