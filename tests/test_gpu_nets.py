@@ -142,3 +142,31 @@ def test_pooled_output_equals_pool2_transform(ops, cin, cout, H, W):
     net2 = ops.Net([sb], {"b": (wb, np.zeros(cout, np.float32))}, torch.bfloat16, DEV)
     _, pb, b2 = net2.layer("b")
     assert torch.equal(ops.conv2d(pooled, sb, pb, b2), ops.conv2d(y, sb, pb, b2, mode="pool2"))
+
+
+@pytest.mark.parametrize("N,H,W", [(1, 64, 96), (2, 40, 56), (1, 24, 8)])
+def test_kernel_predict_equals_layer_chain(ops, N, H, W):
+    """kernel_predict (pooled copies written by the producing layers, heads 0 and 1 fused into
+    the last 3x3 conv of their level) gives the logits of the plain layer-by-layer chain of
+    aps_conv2d_fwd calls (pool2 / up2cat input transforms, separate 1x1 heads) bit for bit."""
+    heads = [43, 34, 25]
+    spec = procgen.unet_spec(16, heads)
+    w = procgen.init_weights(spec, 31)
+    net = ops.Net(spec, w, torch.bfloat16, DEV)
+    g = torch.Generator().manual_seed(H + W)
+    x = torch.randn(N, H, W, 16, generator=g).to(DEV).to(torch.bfloat16)
+    logits = ops.kernel_predict(net, x, heads, torch.bfloat16)
+
+    def conv(name, inp, mode="direct", x2=None, ldy=None):
+        ls, pk, b = net.layer(name)
+        return ops.conv2d(inp, ls, pk, b, mode=mode, x2=x2, ldy=ldy)
+    e0 = conv("enc0b", conv("enc0a", x))
+    e1 = conv("enc1b", conv("enc1a", e0, "pool2"))
+    e2 = conv("enc2b", conv("enc2a", e1, "pool2"))
+    e3 = conv("botb", conv("bota", e2, "pool2"))
+    d2 = conv("dec2b", conv("dec2a", e3, "up2cat", e2))
+    d1 = conv("dec1b", conv("dec1a", d2, "up2cat", e1))
+    d0 = conv("dec0b", conv("dec0a", d1, "up2cat", e0))
+    for l, (f, K) in enumerate(zip([d0, d1, d2], heads)):
+        ref = conv(f"head{l}", f, ldy=ops.round_kstride(K, torch.bfloat16))
+        assert torch.equal(logits[l][..., :K], ref[..., :K]), l
