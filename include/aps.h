@@ -91,12 +91,12 @@ int aps_conv2d_fwd(const void* x, const void* x2, int N, int H, int W, int Cx, i
                    const void* packed_w, const float* bias, int Cout, int ksize, int relu,
                    int dtype, void* y, int ldy, int y_dtype, void* stream);
 
-/* A bf16 (dtype APS_BF16) 3x3 conv (input as aps_conv2d_fwd, Cx + C2 > 16, Cout a multiple
- * of 16 and > 16, H and W even, output row stride Cout) that also writes the 2x2 average pool
- * of its output: pooled [N,H/2,W/2,Cout] bf16, equal bit for bit to the APS_CONV_POOL2 input
- * transform of the next layer applied to y (the U-Net's down path: Sec. 6.3, App. A).
- * Returns APS_ERR_UNSUPPORTED for other shapes or dtypes; the caller then pools in the
- * consumer. */
+/* A 3x3 conv (input as aps_conv2d_fwd, dtype APS_BF16 or APS_F32 for inputs, weights and
+ * outputs, Cx + C2 > 16, Cout a multiple of 16 and > 16, H and W even, output row stride Cout)
+ * that also writes the 2x2 average pool of its output: pooled [N,H/2,W/2,Cout], equal bit for
+ * bit to the APS_CONV_POOL2 input transform of the next layer applied to y (the U-Net's down
+ * path: Sec. 6.3, App. A).  Returns APS_ERR_UNSUPPORTED for other shapes; the caller then pools
+ * in the consumer. */
 int aps_conv2d_fwd_pool(const void* x, const void* x2, int N, int H, int W, int Cx, int C2,
                         int mode, const void* packed_w, const float* bias, int Cout, int relu,
                         int dtype, void* y, void* pooled, void* stream);

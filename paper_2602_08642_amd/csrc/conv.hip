@@ -408,6 +408,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   constexpr int NAV = TM * 9 * 64, NAT = (NAV + 255) / 256;  // weight 16-B vectors per chunk
   __shared__ __attribute__((aligned(16))) uint16_t Xs[SH * SW * PS];
   __shared__ __attribute__((aligned(16))) uint16_t As[NAV * 8];
+  static_assert(!HEAD || SH * SW * PS >= 4 * 16 * (TM * 16 + 8), "head re-layout exceeds Xs");
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const TileId tid_ = xcd_tile(blockIdx.x, a.ntiles, a.nco);
@@ -608,6 +609,266 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
           }
         }
       }
+    }
+  }
+}
+
+// ---- fp32 3x3 convolution with both MFMA operands in LDS --------------------------------------
+// k_conv_lds for fp32 on v_mfma_f32_16x16x4_f32: chunks of 16 input channels (4 per lane per
+// fragment, 4 MFMAs per fragment pair), pixel stride 20 floats in LDS (80 B, conflict-free for the
+// 16 lanes of a B fragment), weights packed by k_pack_f32c16.  Same tiling, row reuse, prefetch
+// and epilogue rules as the bf16 kernel; the pooled copy averages the fp32 outputs in the order of
+// the POOL2 input transform.
+__device__ inline f32x4 mma4(f32x4 a, f32x4 b, f32x4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
+}
+
+// The value of lane l ^ 1 (DPP quad_perm [1,0,3,2]).  By value on purpose: a bit cast applied
+// directly to a vector-element subscript was compiled as a read of element 0.
+__device__ inline float lane_xor1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+}
+
+template <int TM, int TN>
+__device__ inline void lds_epilogue_f32(const ConvArgs& a, f32x4 (&acc)[TM][TN], int row0, int tx0,
+                                        int cob, int n, int lane) {
+  float* y = static_cast<float*>(a.y);
+  float* yp = static_cast<float*>(a.pool);
+  const int col = tx0 + (lane & 15);
+#pragma unroll
+  for (int j0 = 0; j0 < TN; j0 += 2) {
+#pragma unroll
+    for (int m = 0; m < TM; ++m) {
+      const int co = (cob * TM + m) * 16 + 4 * (lane >> 4);
+      if (co >= a.Cout) continue;
+      f32x4 h[2];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int j = j0 + jj, row = row0 + j;
+        f32x4 v = acc[m][j];
+        if (a.relu) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q], 0.f);
+        }
+        h[jj] = v;
+        if (row < a.H && col < a.W) {
+          const float vv[4] = {v[0], v[1], v[2], v[3]};
+          store_out<float>(y + (((size_t)n * a.H + row) * a.W + col) * a.ldy, a.ldy, co, a.Cout, vv);
+        }
+      }
+      if (yp) {
+        f32x4 nb[2];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) nb[jj][q] = lane_xor1(h[jj][q]);
+        const int row = row0 + j0;
+        if ((lane & 1) == 0 && row < a.H && col < a.W)
+          *reinterpret_cast<f32x4*>(yp + (((size_t)n * (a.H / 2) + row / 2) * (a.W / 2) + col / 2) * a.Cout + co) =
+              ((h[0] + nb[0]) + (h[1] + nb[1])) * 0.25f;
+      }
+    }
+  }
+}
+
+template <int MODE, int TM, int TN, bool HEAD>
+__global__ __launch_bounds__(256, 2) void k_conv_lds_f32(ConvArgs a) {
+  constexpr int KC = 16, ROWS = 4 * TN, SH = ROWS + 2, SW = 18, PS = 20;
+  constexpr int NXV = SH * SW * 4, NXT = (NXV + 255) / 256;  // input 16-B vectors per chunk
+  constexpr int NAV = TM * 9 * 64, NAT = (NAV + 255) / 256;  // weight 16-B vectors per chunk
+  // the fused head re-lays each wave's [16 px][16 TM ch] rows out through Xs (row pitch 16 TM + 4)
+  constexpr int XS_TILE = SH * SW * PS, XS_HEAD = HEAD ? 4 * 16 * (TM * 16 + 4) : 0;
+  __shared__ __attribute__((aligned(16))) float Xs[XS_TILE > XS_HEAD ? XS_TILE : XS_HEAD];
+  __shared__ __attribute__((aligned(16))) float As[NAV * 4];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const TileId tid_ = xcd_tile(blockIdx.x, a.ntiles, a.nco);
+  if (tid_.tile >= a.ntiles) return;
+  const int tx0 = (tid_.tile % a.ntx) * 16, ty0 = (tid_.tile / a.ntx) * ROWS;
+  const int cob = tid_.cob, n = blockIdx.z;
+  const float* x = static_cast<const float*>(a.x);
+  const float* x2 = static_cast<const float*>(a.x2);
+  const float* wp = static_cast<const float*>(a.wp);
+  const int Cin = a.Cx + a.C2;
+  // This thread stages channel group g (4 channels) of tile pixels (tid / 4) + 64 k (offsets as
+  // in k_conv_lds, in floats).
+  const int g4 = (tid & 3) * 4;
+  uint32_t xo[NXT], so[MODE == APS_CONV_UP2_CAT ? NXT : 1];
+#pragma unroll
+  for (int k = 0; k < NXT; ++k) {
+    const int p = (tid >> 2) + 64 * k, r = p / SW, col = p - r * SW;
+    const int iy = ty0 - 1 + r, ix = tx0 - 1 + col;
+    const bool in = p < SH * SW && iy >= 0 && iy < a.H && ix >= 0 && ix < a.W;
+    uint32_t o = kNoPixel;
+    if (in) {
+      if constexpr (MODE == APS_CONV_POOL2)
+        o = (uint32_t)((((size_t)n * 2 * a.H + 2 * iy) * (2 * a.W) + 2 * ix) * a.Cx + g4);
+      else if constexpr (MODE == APS_CONV_UP2_CAT)
+        o = (uint32_t)((((size_t)n * (a.H / 2) + iy / 2) * (a.W / 2) + ix / 2) * a.Cx + g4);
+      else
+        o = (uint32_t)((((size_t)n * a.H + iy) * a.W + ix) * a.Cx + g4);
+    }
+    xo[k] = o;
+    if constexpr (MODE == APS_CONV_UP2_CAT)
+      so[k] = in ? (uint32_t)((((size_t)n * a.H + iy) * a.W + ix) * a.C2 + g4) : kNoPixel;
+  }
+  const uint32_t wo = (uint32_t)((((size_t)cob * TM * 9 + wave) * a.nchunk) * 256 + lane * 4);
+  const uint32_t wstep = (uint32_t)(4 * a.nchunk * 256);
+
+  f32x4 px[NXT], pa[NAT];  // clang vector types: HIP's struct vectors are not promoted here
+  uint32_t okbits = 0;
+  const f32x4 zero4 = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto fetch = [&](int c) {
+    const int cb = c * KC;
+    const bool in_ch = cb + g4 < Cin;
+    okbits = 0;
+#pragma unroll
+    for (int k = 0; k < NXT; ++k) {
+      const bool ok = xo[k] != kNoPixel && in_ch;
+      okbits |= (uint32_t)ok << k;
+      if constexpr (MODE == APS_CONV_DIRECT) {
+        px[k] = *reinterpret_cast<const f32x4*>(x + (ok ? xo[k] + cb : 0u));
+      } else if constexpr (MODE == APS_CONV_UP2_CAT) {
+        const float* src = cb + g4 < a.Cx ? x + (xo[k] + cb) : x2 + (so[k] + (cb - a.Cx));
+        px[k] = *reinterpret_cast<const f32x4*>(ok ? src : x);
+      } else {
+        f32x4 v = zero4;
+        if (ok) {
+          if constexpr (MODE == kModeReluMask) {
+            const f32x4 gr = *reinterpret_cast<const f32x4*>(x + (xo[k] + cb));
+            const f32x4 yv = *reinterpret_cast<const f32x4*>(x2 + (xo[k] + cb));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = yv[q] > 0.f ? gr[q] : 0.f;
+          } else {  // APS_CONV_POOL2
+            const uint32_t rs = (uint32_t)(2 * a.W * a.Cx);
+            const uint32_t o = xo[k] + cb;
+            const f32x4 q0 = *reinterpret_cast<const f32x4*>(x + o);
+            const f32x4 q1 = *reinterpret_cast<const f32x4*>(x + (o + a.Cx));
+            const f32x4 q2 = *reinterpret_cast<const f32x4*>(x + (o + rs));
+            const f32x4 q3 = *reinterpret_cast<const f32x4*>(x + (o + rs + a.Cx));
+            v = ((q0 + q1) + (q2 + q3)) * 0.25f;
+          }
+        }
+        px[k] = v;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NAT; ++k)
+      pa[k] = *reinterpret_cast<const f32x4*>(wp + ((tid + 256 * k < NAV ? wo + k * wstep : wo) + c * 256));
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int k = 0; k < NXT; ++k) {
+      const int p = (tid >> 2) + 64 * k;
+      if (p < SH * SW) *reinterpret_cast<f32x4*>(Xs + p * PS + g4) = (okbits >> k) & 1u ? px[k] : zero4;
+    }
+#pragma unroll
+    for (int k = 0; k < NAT; ++k) {
+      const int v = tid + 256 * k;
+      if (v < NAV) *reinterpret_cast<f32x4*>(As + v * 4) = pa[k];
+    }
+  };
+
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m) {
+    f32x4 b0 = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int co0 = (cob * TM + m) * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (a.bias && co0 + q < a.Cout) b0[q] = a.bias[co0 + q];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[m][j] = b0;
+  }
+
+  fetch(0);
+  put();
+  __syncthreads();
+  for (int c = 0; c < a.nchunk; ++c) {
+    const bool more = c + 1 < a.nchunk;
+    if (more) fetch(c + 1);
+    if constexpr (MODE == APS_CONV_POOL2 || MODE == kModeReluMask) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      __builtin_amdgcn_sched_barrier(0);
+      f32x4 A[3][TM];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int m = 0; m < TM; ++m) A[dy][m] = *reinterpret_cast<const f32x4*>(As + ((m * 9 + dy * 3 + dx) * 64 + lane) * 4);
+#pragma unroll
+      for (int ir = 0; ir < TN + 2; ++ir) {
+        const f32x4 B = *reinterpret_cast<const f32x4*>(Xs + ((wave * TN + ir) * SW + (lane & 15) + dx) * PS + (lane >> 4) * 4);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const int j = ir - dy;
+          if (j >= 0 && j < TN) {
+#pragma unroll
+            for (int m = 0; m < TM; ++m) acc[m][j] = mma4(A[dy][m], B, acc[m][j]);
+          }
+        }
+      }
+    }
+    if (more) {
+      __syncthreads();
+      put();
+      __syncthreads();
+    }
+  }
+  if constexpr (HEAD) {
+    __syncthreads();  // the head's re-layout reuses Xs
+    conv_epilogue<float, float, TM, TN, true, true>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
+  } else {
+    lds_epilogue_f32<TM, TN>(a, acc, ty0 + wave * TN, tx0, cob, n, lane);
+  }
+}
+
+template <int MODE, bool HEAD>
+void launch_conv_lds_f32_m(const ConvArgs& a, hipStream_t st) {
+  ConvArgs b = a;
+  b.ntx = (a.W + 15) / 16;
+  b.nchunk = (a.Cx + a.C2 + 15) / 16;
+  // 8-row blocks (TN = 2) for small problems, and for POOL2 with TM = 4, whose 16-row variant
+  // does not fit in 256 VGPRs
+  const bool wide = a.Cout > 32;
+  const bool tn2 = (size_t)a.N * a.H * a.W < 64 * 64 * 8 || (wide && MODE == APS_CONV_POOL2);
+  const int rows = tn2 ? 8 : 16;
+  b.ntiles = b.ntx * ((a.H + rows - 1) / rows);
+  b.nco = wide ? (a.Cout + 63) / 64 : 1;
+  dim3 grid(xcd_grid(b.ntiles, b.nco), 1, a.N);
+  if (!wide) {
+    if (tn2) k_conv_lds_f32<MODE, 2, 2, HEAD><<<grid, 256, 0, st>>>(b);
+    else k_conv_lds_f32<MODE, 2, 4, HEAD><<<grid, 256, 0, st>>>(b);
+  } else if (tn2) {
+    k_conv_lds_f32<MODE, 4, 2, HEAD><<<grid, 256, 0, st>>>(b);
+  } else if constexpr (MODE != APS_CONV_POOL2) {
+    k_conv_lds_f32<MODE, 4, 4, HEAD><<<grid, 256, 0, st>>>(b);
+  }
+}
+
+// Every fp32 3x3 convolution with more than 16 input channels (its weights are packed in
+// 16-channel chunks, which only this kernel reads).  false: 32-bit offsets would overflow.
+template <bool HEAD>
+bool launch_conv_lds_f32(const ConvArgs& a, hipStream_t st) {
+  const size_t px = (size_t)a.N * a.H * a.W;
+  const size_t ex = a.mode == APS_CONV_POOL2 ? 4 * px * a.Cx
+                    : a.mode == APS_CONV_UP2_CAT ? px / 4 * a.Cx : px * a.Cx;
+  const size_t e2 = a.mode == APS_CONV_UP2_CAT ? px * a.C2 : 0;
+  if ((ex > e2 ? ex : e2) + 16 >= ((size_t)1 << 31)) return false;
+  if constexpr (HEAD) {
+    if (a.mode != APS_CONV_DIRECT) return false;
+    launch_conv_lds_f32_m<APS_CONV_DIRECT, true>(a, st);
+    return true;
+  } else {
+    switch (a.mode) {
+      case APS_CONV_DIRECT: launch_conv_lds_f32_m<APS_CONV_DIRECT, false>(a, st); return true;
+      case APS_CONV_POOL2: launch_conv_lds_f32_m<APS_CONV_POOL2, false>(a, st); return true;
+      case APS_CONV_UP2_CAT: launch_conv_lds_f32_m<APS_CONV_UP2_CAT, false>(a, st); return true;
+      case kModeReluMask: launch_conv_lds_f32_m<kModeReluMask, false>(a, st); return true;
+      default: return false;
     }
   }
 }
@@ -833,6 +1094,36 @@ __global__ void k_pack(const float* __restrict__ w, int Cout, int KS, int Cin, i
   else out[i] = v;
 }
 
+// fp32 3x3 layers with more than 16 input channels (the operand of k_conv_lds_f32), in chunks of
+// 16 channels with 4 per lane:
+// packed[(((ct * 9 + tap) * nchunk16 + c) * 64 + lane) * 4 + e] =
+//     w[co = 16 ct + lane % 16][tap][ci = 16 c + 4 (lane / 16) + e]   (0 outside)
+// (transpose as in k_pack).
+__global__ void k_pack_f32c16(const float* __restrict__ w, int Cout, int Cin, int nchunk16,
+                              size_t total, float* __restrict__ out, int transpose) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int e = (int)(i & 3), lane = (int)((i >> 2) & 63);
+  size_t r = i >> 8;
+  const int c = (int)(r % nchunk16);
+  r /= nchunk16;
+  const int tap = (int)(r % 9), ct = (int)(r / 9);
+  const int co = ct * 16 + (lane & 15), ci = c * 16 + (lane >> 4) * 4 + e;
+  float v = 0.f;
+  if (co < Cout && ci < Cin)
+    v = transpose ? w[((size_t)ci * 9 + (8 - tap)) * Cout + co] : w[((size_t)co * 9 + tap) * Cin + ci];
+  out[i] = v;
+}
+
+// fp32 3x3 convolutions with more than 16 input channels run only in k_conv_lds_f32, which
+// addresses its inputs with 32-bit element offsets
+bool fp32_offsets_fit(int mode, int N, int H, int W, int Cx, int C2) {
+  const size_t px = (size_t)N * H * W;
+  const size_t ex = mode == APS_CONV_POOL2 ? 4 * px * Cx : mode == APS_CONV_UP2_CAT ? px / 4 * Cx : px * Cx;
+  const size_t e2 = mode == APS_CONV_UP2_CAT ? px * C2 : 0;
+  return (ex > e2 ? ex : e2) + 16 < ((size_t)1 << 31);
+}
+
 // 8-channel groups of the K layout (see k_conv): merged taps only for 3x3 with <= 16 channels
 int conv_cg(int KS, int Cin) {
   if (KS != 3) return 4;
@@ -865,6 +1156,8 @@ template <typename T, int TM>
 void launch_conv_head(const ConvArgs& a, hipStream_t st) {
   if constexpr (sizeof(T) == 2) {
     if (launch_conv_lds<true>(a, st)) return;
+  } else {
+    if (launch_conv_lds_f32<true>(a, st)) return;
   }
   const bool big = (size_t)a.H * a.W >= 64 * 64;
   const int TN = big ? 4 : 2, TH = 4 * TN;
@@ -881,6 +1174,10 @@ template <typename T, typename TO, int KS, int CG>
 void dispatch_tiles(const ConvArgs& a, hipStream_t st) {
   if constexpr (sizeof(T) == 2 && sizeof(TO) == 2 && KS == 3 && CG == 4) {
     if (launch_conv_lds<false>(a, st)) return;
+  }
+  if constexpr (sizeof(T) == 4 && KS == 3 && CG == 4) {
+    launch_conv_lds_f32<false>(a, st);  // sizes checked by the entry points (fp32_offsets_fit)
+    return;
   }
   const bool big = (size_t)a.H * a.W >= 64 * 64;
   if (a.Cout <= 16) {
@@ -1154,7 +1451,13 @@ static int pack_impl(const float* w, int Cout, int ksize, int Cin, int dtype, vo
   const int nchunk = (ci + kChunk - 1) / kChunk;
   const int blocks = (int)((total + 255) / 256);
   hipStream_t st = as_stream(stream);
-  if (dtype == APS_F32)
+  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, ci) == 4) {
+    // 16-channel chunks (fits in the packed_elems allocation, which counts 32-channel chunks)
+    const int n16 = (ci + 15) / 16;
+    const size_t t16 = (size_t)((co + 16 * kMaxTM - 1) / (16 * kMaxTM)) * kMaxTM * 9 * n16 * 256;
+    k_pack_f32c16<<<(int)((t16 + 255) / 256), 256, 0, st>>>(w, co, ci, n16, t16,
+                                                            static_cast<float*>(packed), transpose);
+  } else if (dtype == APS_F32)
     k_pack<float><<<blocks, 256, 0, st>>>(w, co, ksize, ci, nchunk, total,
                                           static_cast<float*>(packed), transpose, conv_cg(ksize, ci));
   else if (dtype == APS_BF16)
@@ -1212,6 +1515,9 @@ int aps_conv2d_fwd(const void* x, const void* x2, int N, int H, int W, int Cx, i
   a.ldy = ldy;
   a.relu = relu;
   hipStream_t st = as_stream(stream);
+  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, Cx + C2) == 4 &&
+      !fp32_offsets_fit(mode, N, H, W, Cx, C2))
+    return APS_ERR_UNSUPPORTED;
   if (dtype == APS_F32 && y_dtype == APS_F32) dispatch_ks<float, float>(a, ksize, st);
   else if (dtype == APS_BF16 && y_dtype == APS_BF16) dispatch_ks<uint16_t, uint16_t>(a, ksize, st);
   else if (dtype == APS_BF16 && y_dtype == APS_F32) dispatch_ks<uint16_t, float>(a, ksize, st);
@@ -1249,8 +1555,12 @@ int aps_conv2d_bwd_data(const void* dy, const void* ymask, int ldy, int N, int H
   a.Cout = Cin;
   a.nchunk = (ldy + kChunk - 1) / kChunk;
   // the operator was packed for Cout input channels: the padded stride must give the same layout
-  if (a.nchunk != (Cout + kChunk - 1) / kChunk || conv_cg(ksize, ldy) != conv_cg(ksize, Cout))
+  const int kc = dtype == APS_F32 && ksize == 3 && conv_cg(3, ldy) == 4 ? 16 : kChunk;
+  if ((ldy + kc - 1) / kc != (Cout + kc - 1) / kc || conv_cg(ksize, ldy) != conv_cg(ksize, Cout))
     return APS_ERR_SHAPE;
+  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, ldy) == 4 &&
+      !fp32_offsets_fit(a.mode == kModeReluMask ? APS_CONV_DIRECT : a.mode, N, H, W, ldy, 0))
+    return APS_ERR_UNSUPPORTED;
   a.y = dX;
   a.ldy = Cin;
   a.relu = 0;
@@ -1386,7 +1696,7 @@ int aps_conv2d_fwd_pool(const void* x, const void* x2, int N, int H, int W, int 
                         int mode, const void* packed_w, const float* bias, int Cout, int relu,
                         int dtype, void* y, void* pooled, void* stream) {
   if (N < 0 || H < 0 || W < 0 || Cx <= 0 || C2 < 0 || Cout <= 0) return APS_ERR_SHAPE;
-  if (dtype != APS_BF16) return dtype == APS_F32 ? APS_ERR_UNSUPPORTED : APS_ERR_ARG;
+  if (dtype != APS_BF16 && dtype != APS_F32) return APS_ERR_ARG;
   if (H % 2 || W % 2) return APS_ERR_SHAPE;
   if (mode == APS_CONV_UP2_CAT) {
     if (C2 <= 0) return APS_ERR_SHAPE;
@@ -1417,7 +1727,11 @@ int aps_conv2d_fwd_pool(const void* x, const void* x2, int N, int H, int W, int 
   a.ldy = Cout;
   a.relu = relu;
   a.pool = pooled;
-  if (!launch_conv_lds<false>(a, as_stream(stream))) return APS_ERR_UNSUPPORTED;
+  if (dtype == APS_F32) {
+    if (!launch_conv_lds_f32<false>(a, as_stream(stream))) return APS_ERR_UNSUPPORTED;
+  } else if (!launch_conv_lds<false>(a, as_stream(stream))) {
+    return APS_ERR_UNSUPPORTED;
+  }
   APS_LAUNCH_CHECK();
   return APS_OK;
 }
@@ -1463,6 +1777,7 @@ int aps_conv2d_fwd_head(const void* x, const void* x2, int N, int H, int W, int 
   a.hldy = kstride;
   a.store_main = y != nullptr;
   hipStream_t st = as_stream(stream);
+  if (dtype == APS_F32 && !fp32_offsets_fit(mode, N, H, W, Cx, C2)) return APS_ERR_UNSUPPORTED;
   if (dtype == APS_F32) {
     if (Cout == 32) launch_conv_head<float, 2>(a, st); else launch_conv_head<float, 4>(a, st);
   } else if (dtype == APS_BF16) {

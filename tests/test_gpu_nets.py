@@ -111,35 +111,37 @@ def test_fused_sampler_equals_layer_by_layer(ops, cin, dtype, H, W):
         assert torch.allclose(z, zr, rtol=1e-5, atol=1e-5 * float(zr.abs().max()))
 
 
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
 @pytest.mark.parametrize("cin,cout,H,W", [(32, 32, 40, 72), (64, 64, 24, 48), (128, 128, 16, 32),
                                           (32, 64, 8, 16)])
-def test_pooled_output_equals_pool2_transform(ops, cin, cout, H, W):
+def test_pooled_output_equals_pool2_transform(ops, cin, cout, H, W, dtype):
     """aps_conv2d_fwd_pool: y equals the plain conv, pooled equals the 2x2 mean of y taken in
     the POOL2 transform's order, and the next layer reading pooled equals the POOL2 route,
     all bit for bit."""
     from paper_2602_08642_amd import _lib as L
     g = torch.Generator().manual_seed(cin + cout + H)
     N = 2
-    x = torch.randn(N, H, W, cin, generator=g).to(DEV).to(torch.bfloat16)
+    x = torch.randn(N, H, W, cin, generator=g).to(DEV).to(dtype)
     sa = dict(name="a", cin=cin, cout=cout, k=3, relu=True)
     wa = (torch.randn(cout, 3, 3, cin, generator=g) / math.sqrt(9 * cin)).numpy()
     ba = (torch.randn(cout, generator=g) * 0.1).numpy()
-    net = ops.Net([sa], {"a": (wa, ba)}, torch.bfloat16, DEV)
+    net = ops.Net([sa], {"a": (wa, ba)}, dtype, DEV)
     _, pa, bb = net.layer("a")
     ref = ops.conv2d(x, sa, pa, bb)
     y = torch.empty_like(ref)
-    pooled = torch.full((N, H // 2, W // 2, cout), 3.0, dtype=torch.bfloat16, device=DEV)
+    pooled = torch.full((N, H // 2, W // 2, cout), 3.0, dtype=dtype, device=DEV)
     L.check(L.load().aps_conv2d_fwd_pool(ops._p(x), None, N, H, W, cin, 0, L.APS_CONV_DIRECT,
-                                         ops._p(pa), ops._p(bb), cout, 1, L.APS_BF16, ops._p(y),
+                                         ops._p(pa), ops._p(bb), cout, 1,
+                                         L.APS_BF16 if dtype == torch.bfloat16 else L.APS_F32, ops._p(y),
                                          ops._p(pooled), ops._stream()), "fwd_pool")
     assert torch.equal(y, ref)
     q = ref.float().cpu()
     exp = ((q[:, 0::2, 0::2] + q[:, 0::2, 1::2]) + (q[:, 1::2, 0::2] + q[:, 1::2, 1::2])) * 0.25
-    assert torch.equal(pooled.cpu(), exp.to(torch.bfloat16))
+    assert torch.equal(pooled.cpu(), exp.to(dtype))
     # and the next layer reading it directly equals the POOL2 route
     sb = dict(name="b", cin=cout, cout=cout, k=3, relu=True)
     wb = (torch.randn(cout, 3, 3, cout, generator=g) / math.sqrt(9 * cout)).numpy()
-    net2 = ops.Net([sb], {"b": (wb, np.zeros(cout, np.float32))}, torch.bfloat16, DEV)
+    net2 = ops.Net([sb], {"b": (wb, np.zeros(cout, np.float32))}, dtype, DEV)
     _, pb, b2 = net2.layer("b")
     assert torch.equal(ops.conv2d(pooled, sb, pb, b2), ops.conv2d(y, sb, pb, b2, mode="pool2"))
 
