@@ -50,3 +50,28 @@ def normalise(z, budget: float, uniform_frac: float = 1.0 / 8.0):
     sm = e / e.sum(dim=1, keepdim=True)
     s = uniform_frac * budget + (1.0 - uniform_frac) * budget * npx * sm
     return s.reshape(z.shape)
+
+
+def block_mean2(x):
+    """2x2 block mean of NHWC features: out[n, y, x] = mean of x[n, 2y + j, 2x + i], i, j in {0, 1}."""
+    N, H, W, C = x.shape
+    out = torch.zeros((N, H // 2, W // 2, C), dtype=x.dtype)
+    for j in range(2):
+        for i in range(2):
+            out = out + x[:, j::2, i::2, :]
+    return out / 4.0
+
+
+def density_quarter(x, layers, budget: float, uniform_frac: float = 1.0 / 8.0):
+    """Sampler run at a quarter of the pixels (Sec. 7, density-map resolution ablation): the
+    CNN sees the 2x2 block means of the features, its logits are normalised over the
+    (H/2)x(W/2) map with the same per-pixel budget B, and every full-resolution pixel takes
+    the density of its block: s[n, y, x] = s_q[n, y // 2, x // 2].  Each block of 4 pixels
+    then carries 4 s_q, so sum(s) = Npx * B as at full resolution.
+
+    x [N, H, W, C] (H, W even) -> (z_q [N, H/2, W/2], s [N, H, W])
+    """
+    zq = cnn_forward(block_mean2(x), layers)[..., 0]
+    sq = normalise(zq, budget, uniform_frac)
+    s = sq.repeat_interleave(2, dim=1).repeat_interleave(2, dim=2)
+    return zq, s

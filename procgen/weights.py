@@ -38,7 +38,8 @@ def small_kernel_cnn_spec(cin: int = 16, width: int = 16, kout: int = 25):
 def unet_spec(cin: int, head_channels, widths=(32, 64, 128, 256)):
     """4-level U-Net: two 3x3 conv+ReLU per level, 2x2 average-pool down, nearest-2x up and
     concat [upsampled, skip], 1x1 logit heads at decoder levels 0 .. len(head_channels)-1.
-    The head of the bottom level (3) reads the bottleneck output."""
+    The head of the bottom level (3) reads the bottleneck output; a fifth head (level 4, for
+    the five-level pyramid) reads the 2x2 average pool of the bottleneck output."""
     c0, c1, c2, c3 = widths
     s = [
         dict(name="enc0a", cin=cin, cout=c0, k=3, relu=True, gain=1.0),
@@ -56,7 +57,7 @@ def unet_spec(cin: int, head_channels, widths=(32, 64, 128, 256)):
         dict(name="dec0a", cin=c1 + c0, cout=c0, k=3, relu=True, gain=1.0),
         dict(name="dec0b", cin=c0, cout=c0, k=3, relu=True, gain=1.0),
     ]
-    feat_c = [c0, c1, c2, c3]
+    feat_c = [c0, c1, c2, c3, c3]
     for l, K in enumerate(head_channels):
         s.append(dict(name=f"head{l}", cin=feat_c[l], cout=K, k=1, relu=False, gain=0.1))
     return s

@@ -39,6 +39,60 @@ def test_unet_matches_torch_layers():
         assert torch.allclose(ours[l], ref, rtol=1e-11, atol=1e-12)
 
 
+def test_unet_five_heads_matches_torch_layers():
+    """The five-level pyramid's head 4 is a 1x1 conv on the 2x2-pooled bottleneck; heads 0-3
+    are those of the four-head network."""
+    heads = procgen.kernel_channels(5, 5, 2, 5, True)
+    assert heads == [54, 29, 29, 29, 25]                      # App. A: 25 + 4 + 25 at l = 0
+    spec = procgen.unet_spec(16, heads, widths=(8, 8, 16, 16))
+    wts = unet.to_torch(procgen.init_weights(spec, 4))
+    x = torch.randn(1, 32, 48, 16, dtype=torch.float64)
+    ours = unet.unet_forward(x, wts, 5)
+    four = unet.unet_forward(x, wts, 4)
+    for l in range(4):
+        assert torch.equal(ours[l], four[l])
+    r = lambda t, n: Fn.relu(_nchw_conv(t, wts[n], 3))
+    pool = lambda t: Fn.avg_pool2d(t, 2)
+    xc = x.permute(0, 3, 1, 2)
+    e0 = r(r(xc, "enc0a"), "enc0b")
+    e1 = r(r(pool(e0), "enc1a"), "enc1b")
+    e2 = r(r(pool(e1), "enc2a"), "enc2b")
+    e3 = r(r(pool(e2), "bota"), "botb")
+    ref = _nchw_conv(pool(e3), wts["head4"], 1).permute(0, 2, 3, 1)
+    assert ours[4].shape == (1, 2, 3, 25)
+    assert torch.allclose(ours[4], ref, rtol=1e-11, atol=1e-12)
+
+
+def test_density_quarter_pins():
+    """Quarter-resolution density: the budget sum over the full frame, block constancy, the
+    uniform floor, the 2x2 block mean as the CNN input, and a constant CNN giving s = B."""
+    spec = procgen.density_cnn_spec(8)
+    wts = unet.to_torch(procgen.init_weights(spec, 6))
+    layers = [(wts[l["name"]][0], wts[l["name"]][1], l["relu"]) for l in spec]
+    g = torch.Generator().manual_seed(7)
+    x = torch.randn(2, 12, 20, 8, generator=g, dtype=torch.float64)
+    B = 0.25
+    zq, s = density.density_quarter(x, layers, B)
+    assert zq.shape == (2, 6, 10) and s.shape == (2, 12, 20)
+    for n in range(2):
+        assert abs(float(s[n].sum()) - 12 * 20 * B) < 1e-10        # sum(s) = Npx * B
+    assert torch.equal(s[:, 0::2, 0::2], s[:, 1::2, 1::2])
+    assert torch.equal(s[:, 0::2, 0::2], s[:, 0::2, 1::2])
+    assert torch.equal(s[:, 0::2, 0::2], s[:, 1::2, 0::2])
+    assert float(s.min()) >= B / 8 - 1e-15
+    # features constant on 2x2 blocks: the block mean is the block's value
+    xb = x[:, 0::2, 0::2].repeat_interleave(2, dim=1).repeat_interleave(2, dim=2)
+    zqb, _ = density.density_quarter(xb, layers, B)
+    assert torch.allclose(zqb, density.cnn_forward(x[:, 0::2, 0::2], layers)[..., 0], rtol=1e-12, atol=1e-12)
+    # a hand-checked block mean
+    t = torch.arange(16, dtype=torch.float64).reshape(1, 4, 4, 1)
+    assert density.block_mean2(t)[0, :, :, 0].tolist() == [[2.5, 4.5], [10.5, 12.5]]
+    # zero weights: z is the bias everywhere, the softmax is uniform and s = B exactly
+    flat = [(torch.zeros_like(w), torch.full_like(b, 0.3), relu) for w, b, relu in layers]
+    _, s0 = density.density_quarter(x, flat, B)
+    assert torch.allclose(s0, torch.full_like(s0, B), rtol=0, atol=1e-15)
+
+
 def test_density_cnn_matches_torch_layers():
     spec = procgen.density_cnn_spec(8)
     wts = unet.to_torch(procgen.init_weights(spec, 5))
