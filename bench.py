@@ -209,7 +209,8 @@ def bench_config(name, steps, warmup, dev, seed=2602):
         workload=(f"{cfg.name}: {cfg.W}x{cfg.H} frame, {cfg.budget} spp, {cfg.levels}-level kd "
                   f"{cfg.KD}x{cfg.KD} / ku {cfg.KU}x{cfg.KU}"
                   + (f" / kt {cfg.KT}x{cfg.KT}" if cfg.temporal else "")
-                  + f", U-Net 32-64-128-256 ({'fp32' if fp32 else 'bf16'} MFMA)"))
+                  + f", U-Net 32-64-128-256 with {cfg.levels} heads ({'fp32' if fp32 else 'bf16'} MFMA)"
+                  + (", sampler at quarter resolution" if cfg.density_scale == 2 else "")))
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2602_08642_amd", "weights", "c4_trained.npz")
@@ -282,7 +283,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--also", default="c3,c5", help="other configurations timed beside (or '')")
+    ap.add_argument("--also", default="c3,c5,paper", help="other configurations timed beside (or '')")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of the frame the CPU oracle processes (0: the whole frame)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

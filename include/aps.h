@@ -127,6 +127,17 @@ int aps_density_predict(const aps_net* net, const void* feat, int N, int H, int 
                         float budget_spp, float uniform_frac, float* z_out, float* s_out,
                         void* ws, size_t ws_bytes, uint32_t* dev_status, void* stream);
 
+/* Quarter-resolution density map (Sec. 7, density-map resolution): the sampler runs on the
+ * 2x2 block means of the features and each full-resolution pixel takes its block's density.
+ * aps_avgpool2: x [N,H,W,C] -> y [N,H/2,W/2,C], y = ((x00 + x01) + (x10 + x11)) * 0.25 in
+ * float32, stored in dtype (APS_F32 or APS_BF16, round to nearest even); H, W even, C a
+ * multiple of 4.  aps_upsample_nearest2: s_q float32 [N,Hq,Wq] -> s [N,2Hq,2Wq],
+ * s[n][y][x] = s_q[n][y/2][x/2].  Normalising z_q with the full-resolution budget B per pixel
+ * keeps sum(s) = 4 * sum(s_q) = Npx * B.  Device pointers; no workspace; APS_ERR_SHAPE for odd
+ * H or W or C % 4 != 0, APS_ERR_UNSUPPORTED for other dtypes. */
+int aps_avgpool2(const void* x, int N, int H, int W, int C, int dtype, void* y, void* stream);
+int aps_upsample_nearest2(const float* s_q, int N, int Hq, int Wq, float* s, void* stream);
+
 /* ---------------------------------------------------------------- a3: sample mask
  * Sec. 4.2, eq. holdout: count = floor(s) + [u < p], p = s - floor(s) (exact in binary32),
  * u = (Philox4x32-10(key = seed, counter = (pixel, frame, 0, 0)).x >> 8) * 2^-24.
@@ -179,7 +190,9 @@ int aps_assemble_features(int kind, const float* aux, const float* L0, const flo
 /* ---------------------------------------------------------------- a5: kernel prediction
  * U-Net (2 x (3x3 conv + ReLU) per level, 2x2 average pool down, nearest-2x up + concat
  * [up, skip]) with 1x1 heads: logits[l] [N, H>>l, W>>l, kstride[l]] in logit_dtype (F32 or
- * the net's dtype) for l < n_heads.  H, W divisible by 8. */
+ * the net's dtype) for l < n_heads (1..5).  Heads 0-2 read the decoder levels, head 3 the
+ * bottleneck, head 4 (the five-level pyramid of App. A) the 2x2 average pool of the
+ * bottleneck.  H, W divisible by 8 (by 16 with five heads). */
 size_t aps_kernel_predict_workspace_size(const aps_net* net, int N, int H, int W);
 int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W, int C,
                        int n_heads, void* const* logits, int logit_dtype, const int* kstride,

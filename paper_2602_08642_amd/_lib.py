@@ -5,6 +5,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libaps.so")
 
+APS_OK, APS_ERR_NULL, APS_ERR_SHAPE, APS_ERR_UNSUPPORTED, APS_ERR_WORKSPACE, APS_ERR_HIP, APS_ERR_ARG = range(7)
 APS_F32, APS_BF16 = 0, 1
 APS_HARD, APS_RELAXED = 0, 1
 APS_FEAT_SAMPLER, APS_FEAT_KERNEL = 0, 1
@@ -39,6 +40,8 @@ SIGNATURES = {
     "aps_normalize_density": (I, [P, I, I, I, F, F, P, P, SZ, P, P]),
     "aps_density_predict_workspace_size": (SZ, [I, I, I, I, I]),
     "aps_density_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, F, F, P, P, P, SZ, P, P]),
+    "aps_avgpool2": (I, [P, I, I, I, I, I, P, P]),
+    "aps_upsample_nearest2": (I, [P, I, I, I, P, P]),
     "aps_sample_mask_workspace_size": (SZ, [I, I, I]),
     "aps_sample_mask": (I, [P, I, I, I, U64, U32, P, P, P, I64, P, P, P, SZ, P, P]),
     "aps_fixture_render": (I, [P, I, P, P, I, I, I, I64, P, P]),

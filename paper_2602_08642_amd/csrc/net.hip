@@ -27,6 +27,70 @@ int conv(const aps_conv_layer& L, const void* x, const void* x2, int N, int H, i
 
 const int kUnetConvs = 14;
 
+__device__ inline void load4(const float* p, float* a) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a[0] = v.x;
+  a[1] = v.y;
+  a[2] = v.z;
+  a[3] = v.w;
+}
+__device__ inline void load4(const uint16_t* p, float* a) {
+  const u16x4 v = *reinterpret_cast<const u16x4*>(p);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) a[e] = bf2f(v[e]);
+}
+__device__ inline void store4(float* p, const float* v) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ inline void store4(uint16_t* p, const float* v) {
+  *reinterpret_cast<u16x4*>(p) = f2bf4(v[0], v[1], v[2], v[3]);
+}
+
+// 2x2 block mean of NHWC features, four channels per thread, summed in the order of the conv
+// kernels' POOL2 input transform.
+template <typename T>
+__global__ __launch_bounds__(256) void k_avgpool2(const T* __restrict__ x, int N, int Ho, int Wo,
+                                                  int C, T* __restrict__ y) {
+  const int cq = C / 4;
+  const size_t total = (size_t)N * Ho * Wo * cq;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+    const int q = (int)(i % cq);
+    const size_t p = i / cq;
+    const int xo = (int)(p % Wo);
+    const size_t r = p / Wo;
+    const int yo = (int)(r % Ho), n = (int)(r / Ho);
+    const size_t W = 2 * (size_t)Wo;
+    const size_t o00 = (((size_t)n * 2 * Ho + 2 * yo) * W + 2 * xo) * C + 4 * q;
+    float a[4], b[4], c[4], d[4];
+    load4(x + o00, a);
+    load4(x + o00 + C, b);
+    load4(x + o00 + W * C, c);
+    load4(x + o00 + W * C + C, d);
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = ((a[e] + b[e]) + (c[e] + d[e])) * 0.25f;
+    store4(y + p * C + 4 * q, v);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_upsample_nearest2(const float* __restrict__ sq, int N,
+                                                           int Hq, int Wq, float* __restrict__ s) {
+  // one thread per output pair (2x, 2x + 1) of a row
+  const size_t total = (size_t)N * 2 * Hq * Wq;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+    const int xq = (int)(i % Wq);
+    const size_t r = i / Wq;  // output row index over N * 2Hq
+    const int y = (int)(r % (2 * Hq)), n = (int)(r / (2 * Hq));
+    const float v = sq[((size_t)n * Hq + y / 2) * Wq + xq];
+    *reinterpret_cast<float2*>(s + r * 2 * Wq + 2 * xq) = make_float2(v, v);
+  }
+}
+
+int grid_for(size_t items) {
+  const size_t b = (items + 255) / 256;
+  return (int)(b < 65536 ? (b ? b : 1) : 65536);
+}
+
 }  // namespace
 
 extern "C" {
@@ -77,6 +141,32 @@ int aps_density_predict(const aps_net* net, const void* feat, int N, int H, int 
                                aps_normalize_workspace_size(N, H, W), dev_status, stream);
 }
 
+int aps_avgpool2(const void* x, int N, int H, int W, int C, int dtype, void* y, void* stream) {
+  if (N < 0 || H < 0 || W < 0 || C <= 0 || H % 2 || W % 2 || C % 4) return APS_ERR_SHAPE;
+  if (dtype != APS_F32 && dtype != APS_BF16) return APS_ERR_UNSUPPORTED;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!x || !y) return APS_ERR_NULL;
+  const size_t items = (size_t)N * (H / 2) * (W / 2) * (C / 4);
+  if (dtype == APS_F32)
+    k_avgpool2<float><<<grid_for(items), 256, 0, as_stream(stream)>>>(
+        static_cast<const float*>(x), N, H / 2, W / 2, C, static_cast<float*>(y));
+  else
+    k_avgpool2<uint16_t><<<grid_for(items), 256, 0, as_stream(stream)>>>(
+        static_cast<const uint16_t*>(x), N, H / 2, W / 2, C, static_cast<uint16_t*>(y));
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
+int aps_upsample_nearest2(const float* s_q, int N, int Hq, int Wq, float* s, void* stream) {
+  if (N < 0 || Hq < 0 || Wq < 0) return APS_ERR_SHAPE;
+  if ((size_t)N * Hq * Wq == 0) return APS_OK;
+  if (!s_q || !s) return APS_ERR_NULL;
+  const size_t items = (size_t)N * 2 * Hq * Wq;
+  k_upsample_nearest2<<<grid_for(items), 256, 0, as_stream(stream)>>>(s_q, N, Hq, Wq, s);
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
 size_t aps_kernel_predict_workspace_size(const aps_net* net, int N, int H, int W) {
   if (!net || net->n_layers < kUnetConvs + 1) return 0;
   const aps_conv_layer* L = net->layer;
@@ -105,8 +195,9 @@ int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W
                        int n_heads, void* const* logits, int logit_dtype, const int* kstride,
                        void* ws, size_t ws_bytes, void* stream) {
   if (!net) return APS_ERR_NULL;
-  if (n_heads < 1 || n_heads > 4 || net->n_layers != kUnetConvs + n_heads) return APS_ERR_SHAPE;
-  if (N < 0 || H < 0 || W < 0 || H % 8 || W % 8) return APS_ERR_SHAPE;
+  if (n_heads < 1 || n_heads > 5 || net->n_layers != kUnetConvs + n_heads) return APS_ERR_SHAPE;
+  const int div = n_heads > 4 ? 16 : 8;
+  if (N < 0 || H < 0 || W < 0 || H % div || W % div) return APS_ERR_SHAPE;
   if ((size_t)N * H * W == 0) return APS_OK;
   if (!feat || !logits || !kstride) return APS_ERR_NULL;
   const int dt = net->dtype;
@@ -202,13 +293,14 @@ int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W
   }
   if (!fused0)
     APS_TRY(conv(L[13], t, nullptr, N, H, W, L[12].cout, 0, APS_CONV_DIRECT, dt, d0, c0, dt, stream));
-  // remaining 1x1 heads
-  const void* feats[4] = {d0, d1, d2, e3};
-  const int fc[4] = {c0, c1, c2, c3};
+  // remaining 1x1 heads (head 4 reads the bottleneck through the 2x2-pool input transform)
+  const void* feats[5] = {d0, d1, d2, e3, e3};
+  const int fc[5] = {c0, c1, c2, c3, c3};
   for (int l = 0; l < n_heads; ++l) {
     if ((l == 0 && fused0) || (l == 1 && fused1)) continue;
     APS_TRY(conv(L[kUnetConvs + l], feats[l], nullptr, N, H >> l, W >> l, fc[l], 0,
-                 APS_CONV_DIRECT, dt, logits[l], kstride[l], logit_dtype, stream));
+                 l == 4 ? APS_CONV_POOL2 : APS_CONV_DIRECT, dt, logits[l], kstride[l],
+                 logit_dtype, stream));
   }
   return APS_OK;
 }

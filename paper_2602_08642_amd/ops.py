@@ -232,6 +232,24 @@ def density_predict(net: Net, feat, budget: float, uniform_frac: float = 1.0 / 8
     return z, s
 
 
+def avgpool2(x):
+    """[N,H,W,C] -> [N,H/2,W/2,C] 2x2 block means (quarter-resolution sampler input)."""
+    _need(x, "x")
+    N, H, W, Cx = x.shape
+    y = torch.empty((N, H // 2, W // 2, Cx), dtype=x.dtype, device=x.device)
+    L.check(L.load().aps_avgpool2(_p(x), N, H, W, Cx, _dt(x.dtype), _p(y), _stream()), "avgpool2")
+    return y
+
+
+def upsample_nearest2(s_q):
+    """[N,Hq,Wq] float32 -> [N,2Hq,2Wq]: every pixel takes its 2x2 block's value."""
+    _need(s_q, "s_q", _F32)
+    N, Hq, Wq = s_q.shape
+    s = torch.empty((N, 2 * Hq, 2 * Wq), dtype=_F32, device=s_q.device)
+    L.check(L.load().aps_upsample_nearest2(_p(s_q), N, Hq, Wq, _p(s), _stream()), "upsample_nearest2")
+    return s
+
+
 def round_kstride(K: int, dtype) -> int:
     v = 8 if dtype == _BF16 else 4
     return (K + v - 1) // v * v
@@ -247,8 +265,8 @@ def kernel_predict(net: Net, feat, head_channels, logit_dtype=_F32):
     lib = L.load()
     nb = lib.aps_kernel_predict_workspace_size(C.byref(net.desc), N, H, W)
     ws = WS.get(nb, feat.device)
-    arr = (C.c_void_p * 4)(*[t.data_ptr() for t in logits])
-    karr = (C.c_int * 4)(*ks)
+    arr = (C.c_void_p * 5)(*[t.data_ptr() for t in logits])
+    karr = (C.c_int * 5)(*ks)
     L.check(lib.aps_kernel_predict(C.byref(net.desc), _p(feat), N, H, W, Cf, n, arr,
                                    _dt(logit_dtype), karr, _p(ws), nb, _stream()), "kernel_predict")
     return logits

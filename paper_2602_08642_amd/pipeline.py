@@ -31,6 +31,7 @@ class FrameConfig:
     widths: tuple = (32, 64, 128, 256)
     uniform_frac: float = 1.0 / 8.0   # Sec. 3: 1/8 of the budget spread uniformly
     kernel_net: str = "unet"          # "unet" or "cnn3" (single-level 3-layer CNN)
+    density_scale: int = 1            # 2: sampler at a quarter of the pixels (Sec. 7)
 
     @property
     def sampler_cin(self) -> int:
@@ -61,6 +62,10 @@ CONFIGS = {
     "c4": FrameConfig("c4", 256, 256, 0.25, 3, 5, 3, 3, True, BF16, BF16),
     # 4K, 0.125 spp, 4-level 7x7 pyramid, BF16 U-Net, temporal
     "c5": FrameConfig("c5", 2160, 3840, 0.125, 4, 7, 3, 3, True, BF16, BF16),
+    # the paper's own reconstruction (App. A): 5 levels, kd 5x5 everywhere, literal 2x2 ku,
+    # kt 5x5 (54-way softmax at level 0), with the quarter-resolution density map of Sec. 7;
+    # 1080 rows are not divisible by 2^4, so the frame is 1080p padded to 1088 rows
+    "paper": FrameConfig("paper", 1088, 1920, 0.25, 5, 5, 2, 5, True, BF16, BF16, density_scale=2),
 }
 
 
@@ -104,6 +109,10 @@ class FrameRenderer:
             return torch.full((N, cfg.H, cfg.W), cfg.budget, dtype=F32, device=self.device)
         feat = ops.assemble_features("sampler", aux, prev=prev, mv=mv, C_out=cfg.sampler_cin,
                                      dtype=cfg.net_dtype)
+        if cfg.density_scale == 2:
+            # quarter resolution: the budget per pixel is unchanged, so sum(s) stays Npx * B
+            _, s_q = ops.density_predict(self.dnet, ops.avgpool2(feat), cfg.budget, cfg.uniform_frac)
+            return ops.upsample_nearest2(s_q)
         _, s = ops.density_predict(self.dnet, feat, cfg.budget, cfg.uniform_frac)
         return s
 

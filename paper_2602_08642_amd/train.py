@@ -101,6 +101,8 @@ class TrainNet:
 
 
 def density_forward(net: TrainNet, cfg: FrameConfig, aux, prev, mv):
+    if cfg.density_scale != 1:
+        raise NotImplementedError("training runs the sampler at full resolution")
     feat = ag.Features.apply("sampler", aux, None, None, prev, mv, cfg.sampler_cin, cfg.net_dtype)
     L = net.layers
     h = ag.conv(feat, L["d0"])
@@ -126,9 +128,9 @@ def unet_forward(net: TrainNet, cfg: FrameConfig, feat):
     d1 = ag.conv(t, L["dec1b"])
     t = ag.conv(d1, L["dec0a"], "up2cat", x2=e0)
     d0 = ag.conv(t, L["dec0b"])
-    feats = [d0, d1, d2, e3]
+    feats = [d0, d1, d2, e3, e3]
     ks = cfg.head_channels()
-    return [ag.conv(feats[l], L[f"head{l}"], out_dtype=cfg.logit_dtype,
+    return [ag.conv(feats[l], L[f"head{l}"], "pool2" if l == 4 else "direct", out_dtype=cfg.logit_dtype,
                     ldy=ops.round_kstride(ks[l], cfg.logit_dtype)) for l in range(cfg.levels)]
 
 

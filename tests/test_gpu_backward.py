@@ -177,6 +177,7 @@ def test_features_backward(ops, kind):
     ("pool2", 1, 12, 20, 32, 0, 64, 3, True),
     ("up2cat", 1, 16, 24, 64, 32, 32, 3, True),
     ("direct", 1, 18, 30, 16, 0, 1, 3, False),
+    ("pool2", 1, 4, 6, 32, 0, 25, 1, False),          # the five-level pyramid's coarsest head
 ])
 def test_conv_backward(ops, cfg, dtype):
     mode, N, H, W, Cx, C2, Cout, k, relu = cfg

@@ -1,6 +1,7 @@
 """Parity at the benchmark's full sizes, in the launch configurations bench.py times: the 1080p
-U-Net (bf16 as in C3, fp32 as in C2), the fused sampler CNN at 1080p and the C3 gathering pyramid
-(bf16 logits, temporal term), each against the FP64 oracle over the whole frame."""
+U-Net (bf16 as in C3, fp32 as in C2), the fused sampler CNN at 1080p and the gathering pyramids
+of C3 and of the paper configuration (bf16 logits, temporal term), each against the FP64 oracle
+over the whole frame."""
 import numpy as np
 import pytest
 import torch
@@ -55,9 +56,15 @@ def test_sampler_1080p_matches_oracle(ops, cin, dtype, tol):
     assert rel_norm(s.cpu(), sr) < 1e-6
 
 
-def test_denoise_pyramid_1080p_c3(ops):
-    """C3 reconstruction: 3 levels, kd 5x5, ku 3x3, kt 3x3, bf16 logits, warped history."""
-    levels, KD, KU, KT = 3, 5, 3, 3
+@pytest.mark.parametrize("case", [
+    # C3 reconstruction: 3 levels, kd 5x5, ku 3x3, kt 3x3, bf16 logits, warped history
+    (1080, 3, 5, 3, 3),
+    # the paper's reconstruction (App. A) on 1080p padded to 1088 rows: 5 levels, kd 5x5,
+    # the printed 2x2 ku, kt 5x5
+    (1088, 5, 5, 2, 5),
+])
+def test_denoise_pyramid_fullsize(ops, case):
+    H, levels, KD, KU, KT = case
     g = torch.Generator().manual_seed(23)
     Ls = [torch.randn(1, H >> l, W >> l, 4, generator=g) * 2.0 for l in range(levels)]
     for t in Ls:
@@ -78,5 +85,5 @@ def test_denoise_pyramid_1080p_c3(ops):
     z64 = [t.double() for t in logits]
     ref = ofilt.denoise_pyramid(L64, z64, KD, KU, KT, prev.double(), mv.double())[0]
     mag = ofilt.denoise_magnitude(L64, z64, KD, KU, KT, prev.double(), mv.double())[0]
-    assert_mag_close(out[..., :3], ref[..., :3], mag[..., :3], 1e-5, what="1080p c3")
+    assert_mag_close(out[..., :3], ref[..., :3], mag[..., :3], 1e-5, what=str(case))
     assert torch.all(out[..., 3] == 0)
