@@ -10,13 +10,17 @@
   clamp(lambda * (p - u) / p, 0, 1), non-zero iff u < p, so the relaxed forward takes
   exactly the samples of the hard mask drawn from the same u.
 * App. A, eq. app-pyramid: level l is the mean of L_noisy over 2^l x 2^l blocks.
+* u: Philox (one counter per pixel), or a blue-noise threshold texture (Sec. 6.3 uses
+  blue-noise dithering) tiled over the frame with a toroidal offset per image and frame:
+  u[n, y, x] = tex[(y + oy) mod T, (x + ox) mod T], (ox, oy) = (word0, word1) mod T of
+  Philox with counter (n, frame, 2, 0).
 
 Counts, offsets and the compact list are exact integer results.
 """
 import numpy as np
 import torch
 
-from .philox import uniform24
+from .philox import philox4x32_10, uniform24
 
 BLOCK = 256          # pixels per block of the per-block exclusive offsets
 COUNT_MAX = 255      # counts are stored as uint8
@@ -26,8 +30,35 @@ def pixel_index(N, H, W):
     return np.arange(N * H * W, dtype=np.uint64).reshape(N, H, W)
 
 
-def mask(s32, seed: int, frame: int):
-    """s32: float32 [N, H, W] densities.
+STREAM_TEX_OFFSET = 2
+
+
+def tex_offsets(seed: int, n: int, frame: int, T: int):
+    """(ox, oy) of image n at this frame: Philox words 0 and 1 of counter (n, frame, 2, 0) mod T."""
+    seed = int(seed)
+    w = philox4x32_10(np.uint64(n), np.uint64(frame), np.uint64(STREAM_TEX_OFFSET), np.uint64(0),
+                      seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    return int(w[0]) % T, int(w[1]) % T
+
+
+def u_values(N, H, W, seed: int, frame: int, u_tex=None):
+    """u [N, H, W] float64: Philox per pixel, or the tiled texture with per-image offsets."""
+    if u_tex is None:
+        return uniform24(seed, pixel_index(N, H, W), frame)
+    tex = np.asarray(u_tex, dtype=np.float32).astype(np.float64)
+    T = tex.shape[0]
+    assert tex.shape == (T, T)
+    u = np.empty((N, H, W))
+    for n in range(N):
+        ox, oy = tex_offsets(seed, n, frame, T)
+        for y in range(H):
+            for x in range(W):
+                u[n, y, x] = tex[(y + oy) % T, (x + ox) % T]
+    return u
+
+
+def mask(s32, seed: int, frame: int, u_tex=None):
+    """s32: float32 [N, H, W] densities; u_tex: optional float32 [T, T] threshold texture.
 
     Returns dict(count uint8 [N,H,W], p float64 [N,H,W] (exact), u float64, take bool,
     block_offset int64 [ceil(Npix/256)+1] (exclusive; last entry = total),
@@ -37,7 +68,7 @@ def mask(s32, seed: int, frame: int):
     N, H, W = s.shape
     fl = np.floor(s)
     p = s - fl                                                 # exact
-    u = uniform24(seed, pixel_index(N, H, W), frame)
+    u = u_values(N, H, W, seed, frame, u_tex)
     take = u < p
     cnt = fl + take
     overflow = bool((cnt > COUNT_MAX).any())
@@ -68,7 +99,8 @@ def relaxed_ramp(p, u, lam: float):
     return torch.where(p > 0, r, torch.zeros_like(r))
 
 
-def scatter(s, count, samples, seed: int, frame: int, mode: str = "hard", lam: float = 10.0):
+def scatter(s, count, samples, seed: int, frame: int, mode: str = "hard", lam: float = 10.0,
+            u_tex=None):
     """Sec. 4.2 eq. stoch_rnoisy (hard) / Sec. 4.3 eq. relaxed_holdout (relaxed): L_noisy [N, H, W, 4] (channel 3 = 0) from samples delivered in request order.
 
     s: [N, H, W] densities (torch float64 for autograd, or numpy; the floor and the
@@ -95,7 +127,7 @@ def scatter(s, count, samples, seed: int, frame: int, mode: str = "hard", lam: f
         H_i = hold
     elif mode == "relaxed":
         p = sf - torch.as_tensor(fl)                           # gradient of p w.r.t. s is 1
-        u = torch.as_tensor(uniform24(seed, np.arange(cnt.size, dtype=np.uint64), frame))
+        u = torch.as_tensor(u_values(N, H, W, seed, frame, u_tex).reshape(-1))
         H_i = hold * (h_factor(lam) * relaxed_ramp(p, u, lam))[:, None]
     else:
         raise ValueError(mode)

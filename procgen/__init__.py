@@ -11,7 +11,9 @@ normalisation, sampling, scatter or filtering).  It only makes inputs:
   n = lognormal(0, 0.8) - E[lognormal(0, 0.8)]  (zero-mean multiplicative noise with
   firefly tails), standing in for the paper's pre-rendered path-traced samples
   (Sec. 3, last paragraph: samples are pre-rendered and combined into any budget),
-* seeded random-init network weights (Kaiming-uniform).
+* seeded random-init network weights (Kaiming-uniform),
+* a blue-noise threshold texture by void-and-cluster (the table of u the sampling step can
+  draw from instead of Philox).
 
 Everything is NumPy and addressed by integer seeds, so the same call gives the same
 arrays on any machine.
@@ -26,3 +28,4 @@ __all__ = [
     "FrameData", "density_cnn_spec", "unet_spec", "small_kernel_cnn_spec", "init_weights",
     "kernel_channels",
 ]
+from .bluenoise import void_and_cluster, blue_noise_thresholds

@@ -211,3 +211,82 @@ def test_pyramid_matches_avg_pool():
         assert torch.allclose(pyr[l], ref, rtol=1e-13, atol=1e-14)
     c = torch.full((1, 8, 8, 4), 1.7, dtype=torch.float64)
     assert all(torch.allclose(p, torch.full_like(p, 1.7)) for p in sampling.pyramid(c, 3))
+
+
+# ------------------------------------------------------------------ blue-noise u
+
+def test_blue_noise_texture_properties():
+    import procgen
+    T = 64
+    r = procgen.void_and_cluster(T)
+    assert sorted(r.ravel().tolist()) == list(range(T * T))
+    u = procgen.blue_noise_thresholds(T)
+    assert np.array_equal(u.astype(np.float64), (r + 0.5) / (T * T))     # exact in binary32
+    # blue: the lowest frequencies carry almost no power (white noise: about 1/12 * T^2 each)
+    F = np.abs(np.fft.fft2(u - u.mean())) ** 2
+    low = [(0, 1), (1, 0), (1, 1), (0, 2), (2, 0), (1, 2), (2, 1), (2, 2)]
+    assert sum(F[a, b] for a, b in low) < 1e-3 * len(low) * T * T / 12
+    # well spread: the sparsest 1/16 of the thresholds keeps every pair >= 2 px apart (torus)
+    pts = np.argwhere(r < T * T // 16)
+    d = np.abs(pts[:, None, :] - pts[None, :, :])
+    d = np.minimum(d, T - d)
+    dist = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(dist, 99)
+    assert dist.min() >= 2.0
+
+
+def test_mask_texture_stratification():
+    """For constant p every T x T window of u holds each threshold once, so it takes exactly
+    ceil(p T^2 - 1/2) holdouts: the blue-noise mask is stratified, not just unbiased."""
+    import procgen
+    T = 16
+    tex = procgen.blue_noise_thresholds(T, seed=3)
+    N, H, W = 2, 40, 52
+    for k, p in ((0, 0.25), (1, 0.3), (2, 0.8125)):
+        s = np.full((N, H, W), k + p, np.float32)
+        m = sampling.mask(s, 99, 5, u_tex=tex)
+        c = m["count"].astype(np.int64)
+        want = T * T * k + math.ceil(p * T * T - 0.5)
+        for n in range(N):
+            for y0, x0 in ((0, 0), (3, 7), (H - T, W - T), (11, 30)):
+                assert int(c[n, y0:y0 + T, x0:x0 + T].sum()) == want
+
+
+def test_mask_texture_lookup_orientation():
+    """Rows of u are rows of the texture, cyclically shifted: a transposed or mirrored lookup
+    fails; offsets change with the frame and the image."""
+    import procgen
+    T = 16
+    tex = procgen.blue_noise_thresholds(T, seed=4).astype(np.float64)
+    u = sampling.u_values(2, 24, 40, 7, 9, tex)
+    for n in range(2):
+        shifts = []
+        for y in range(24):
+            row = u[n, y, :T]
+            hits = [(ty, sh) for ty in range(T) for sh in range(T) if np.array_equal(np.roll(tex[ty], -sh), row)]
+            assert len(hits) == 1
+            shifts.append(hits[0])
+        oy, ox = shifts[0]
+        assert all(h == ((oy + y) % T, ox) for y, h in enumerate(shifts))
+        # x continues past the tile: column T + x repeats column x
+        assert np.array_equal(u[n, :, T:2 * T], u[n, :, :T])
+    offs = {sampling.tex_offsets(7, n, f, T) for n in range(2) for f in range(16)}
+    assert len(offs) >= 20
+
+
+def test_scatter_texture_relaxed_limit_is_hard():
+    """With texture u the relaxed holdout weight is h * ramp with the same u: as lambda grows it
+    tends to the hard holdout of the mask drawn from that u."""
+    import procgen
+    T = 16
+    tex = procgen.blue_noise_thresholds(T, seed=5)
+    rng = np.random.default_rng(3)
+    N, H, W = 1, 20, 24
+    s = (rng.random((N, H, W)) * 2.5 + 0.05).astype(np.float32)
+    m = sampling.mask(s, 21, 2, u_tex=tex)
+    smp = rng.normal(1.0, 0.5, (m["total"], 4))
+    hard = sampling.scatter(s.astype(np.float64), m["count"], smp, 21, 2, "hard", u_tex=tex)
+    rel = sampling.scatter(s.astype(np.float64), m["count"], smp, 21, 2, "relaxed", 1e7, u_tex=tex)
+    assert torch.allclose(rel, hard, rtol=1e-5, atol=1e-6)
+    # and the Philox u would have given another mask
+    assert not np.array_equal(sampling.mask(s, 21, 2)["count"], m["count"])
