@@ -151,7 +151,7 @@ def bench_config(name, steps, warmup, dev, seed=2602):
         req = r.request(s, seed, frame)
         mark(2)
         Ls = ops.scatter_samples(s, req["count"], req["pixel_offset"], smp, cfg.levels, "hard",
-                                 10.0, seed, frame)
+                                 10.0, seed, frame, u_tex=r.u_tex)
         mark(3)
         if r.knet is not None:
             feat = ops.assemble_features("kernel", aux, Ls[0], s, prev, mv, cfg.kernel_cin, cfg.net_dtype)
@@ -210,7 +210,8 @@ def bench_config(name, steps, warmup, dev, seed=2602):
                   f"{cfg.KD}x{cfg.KD} / ku {cfg.KU}x{cfg.KU}"
                   + (f" / kt {cfg.KT}x{cfg.KT}" if cfg.temporal else "")
                   + f", U-Net 32-64-128-256 with {cfg.levels} heads ({'fp32' if fp32 else 'bf16'} MFMA)"
-                  + (", sampler at quarter resolution" if cfg.density_scale == 2 else "")))
+                  + (", sampler at quarter resolution" if cfg.density_scale == 2 else "")
+                  + (", blue-noise u" if cfg.u_noise == "blue" else "")))
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2602_08642_amd", "weights", "c4_trained.npz")

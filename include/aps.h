@@ -153,6 +153,18 @@ int aps_sample_mask(const float* s, int N, int H, int W, uint64_t seed, uint32_t
                     int64_t capacity, int32_t* total, float* p_out, void* ws, size_t ws_bytes,
                     uint32_t* dev_status, void* stream);
 
+/* The same mask with u from a blue-noise threshold texture (Sec. 6.3 dithers with blue noise):
+ * u_tex float32 [tex_size][tex_size] on the device (e.g. void-and-cluster thresholds
+ * (rank + 1/2) / tex_size^2), tiled over each image with a toroidal offset per image and frame,
+ * (ox, oy) = (word0, word1) mod tex_size of Philox4x32-10(key = seed, counter = (n, frame, 2, 0)):
+ * u[n][y][x] = u_tex[(y + oy) mod T][(x + ox) mod T].  u_tex == NULL gives the Philox u above.
+ * APS_ERR_ARG when u_tex is given and tex_size is outside 1..4096.  The caller keeps u_tex
+ * alive until the work on the stream has finished. */
+int aps_sample_mask_tex(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                        const float* u_tex, int tex_size, uint8_t* count, int32_t* pixel_offset,
+                        int32_t* sample_pixel, int64_t capacity, int32_t* total, float* p_out,
+                        void* ws, size_t ws_bytes, uint32_t* dev_status, void* stream);
+
 /* Renderer stand-in (not part of the method): writes sample j of pixel i as
  * pool[i][j mod J] (pool float32 [N*H*W][J][4]) at samples[pixel_offset[i] + j]. */
 int aps_fixture_render(const float* pool, int J, const uint8_t* count,
@@ -175,6 +187,12 @@ int aps_scatter_samples(const float* s, const uint8_t* count, const int32_t* pix
                         int mode,
                         float lambda, uint64_t seed, uint32_t frame, float* const* L,
                         void* stream);
+/* aps_scatter_samples with the relaxed holdout's u from a blue-noise texture, as
+ * aps_sample_mask_tex (pass the texture the mask was drawn with). */
+int aps_scatter_samples_tex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                            const float* samples, int64_t n_samples, int N, int H, int W,
+                            int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
+                            const float* u_tex, int tex_size, float* const* L, void* stream);
 
 /* Network inputs (C <= 16 channels, zero padded), out [N,H,W,C] in out_dtype.
  *   APS_FEAT_SAMPLER: aux[0..6], then with prev: tonemap(W prev) RGB, valid
@@ -264,6 +282,12 @@ int aps_scatter_samples_bwd(const float* s, const uint8_t* count, const int32_t*
                             int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
                             const float* const* grad_L, float* grad_s, int accumulate,
                             void* stream);
+/* aps_scatter_samples_bwd with u from a blue-noise texture, as aps_sample_mask_tex. */
+int aps_scatter_samples_bwd_tex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                                const float* samples, int64_t n_samples, int N, int H, int W,
+                                int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
+                                const float* u_tex, int tex_size, const float* const* grad_L,
+                                float* grad_s, int accumulate, void* stream);
 
 /* Budget normalisation backward (Sec. 3): grad_z (written) = c1 sm (g - sum(sm g)) per frame,
  * c1 = (1-f) B Npx; fixed-tree reductions (deterministic). */

@@ -51,9 +51,9 @@ def u_values(N, H, W, seed: int, frame: int, u_tex=None):
     u = np.empty((N, H, W))
     for n in range(N):
         ox, oy = tex_offsets(seed, n, frame, T)
-        for y in range(H):
-            for x in range(W):
-                u[n, y, x] = tex[(y + oy) % T, (x + ox) % T]
+        rows = (np.arange(H) + oy) % T          # texture row of each image row
+        cols = (np.arange(W) + ox) % T          # texture column of each image column
+        u[n] = tex[np.ix_(rows, cols)]
     return u
 
 

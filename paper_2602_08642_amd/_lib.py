@@ -44,8 +44,10 @@ SIGNATURES = {
     "aps_upsample_nearest2": (I, [P, I, I, I, P, P]),
     "aps_sample_mask_workspace_size": (SZ, [I, I, I]),
     "aps_sample_mask": (I, [P, I, I, I, U64, U32, P, P, P, I64, P, P, P, SZ, P, P]),
+    "aps_sample_mask_tex": (I, [P, I, I, I, U64, U32, P, I, P, P, P, I64, P, P, P, SZ, P, P]),
     "aps_fixture_render": (I, [P, I, P, P, I, I, I, I64, P, P]),
     "aps_scatter_samples": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P]),
+    "aps_scatter_samples_tex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P]),
     "aps_assemble_features": (I, [I, P, P, P, P, P, I, I, I, I, I, P, P]),
     "aps_kernel_predict_workspace_size": (SZ, [C.POINTER(NetDesc), I, I, I]),
     "aps_kernel_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, I, P, I, P, P, SZ, P]),
@@ -58,6 +60,7 @@ SIGNATURES = {
     "aps_denoise_pyramid_bwd": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, P, P, I, P, P, P, P,
                                     SZ, P]),
     "aps_scatter_samples_bwd": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P, I, P]),
+    "aps_scatter_samples_bwd_tex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P, I, P]),
     "aps_normalize_bwd_workspace_size": (SZ, [I, I, I]),
     "aps_normalize_density_bwd": (I, [P, I, I, I, F, F, P, P, P, SZ, P]),
     "aps_assemble_features_bwd": (I, [I, P, P, P, I, I, I, I, I, P, P, P, P, P]),

@@ -72,6 +72,23 @@ __device__ inline float uniform24(uint64_t seed, uint32_t pixel, uint32_t frame)
   return (float)(r.x >> 8) * 0x1p-24f;
 }
 
+// u of the sampling step: Philox per pixel (tex == nullptr), or a T x T threshold texture
+// tiled over each image with a toroidal offset (ox, oy) = (word0, word1) mod T of Philox with
+// counter (image, frame, stream 2, 0): u = tex[(y + oy) mod T][(x + ox) mod T].
+struct USource {
+  const float* tex;
+  uint32_t T, H, W;
+};
+__device__ inline float draw_u(const USource& us, uint64_t seed, uint32_t pixel, uint32_t frame) {
+  if (!us.tex) return uniform24(seed, pixel, frame);
+  const uint32_t hw = us.H * us.W;
+  const uint32_t n = pixel / hw, r = pixel - n * hw;
+  const uint32_t y = r / us.W, x = r - y * us.W;
+  const uint4 w = philox4x32_10(make_uint4(n, frame, 2u, 0u), (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint32_t ox = w.x % us.T, oy = w.y % us.T;
+  return us.tex[((y + oy) % us.T) * us.T + (x + ox) % us.T];
+}
+
 // ---- wave / block reductions (wave64) -------------------------------------------------
 __device__ inline float wave_sum(float v) {
 #pragma unroll

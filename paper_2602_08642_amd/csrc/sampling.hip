@@ -13,6 +13,7 @@ namespace {
 
 constexpr int kNormElems = 2048;  // pixels per block of the softmax partial reductions
 constexpr int kMaskBlock = 256;   // pixels per block of the sample-list offsets
+constexpr int kMaxTexSize = 4096;  // largest blue-noise texture side accepted
 
 // ------------------------------------------------------------------ normalisation
 // Partial (max, sum exp(z - max)) over kNormElems pixels of one image; fixed partition,
@@ -85,6 +86,7 @@ __global__ __launch_bounds__(256) void k_norm_apply(const float* __restrict__ z,
 // ------------------------------------------------------------------ sample mask
 __global__ __launch_bounds__(kMaskBlock) void k_mask_count(const float* __restrict__ s,
                                                            int npix, uint64_t seed, uint32_t frame,
+                                                           USource us,
                                                            uint8_t* __restrict__ count,
                                                            float* __restrict__ p_out,
                                                            int32_t* __restrict__ block_sum,
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(kMaskBlock) void k_mask_count(const float* __restri
     } else {
       const float fl = floorf(si);
       p = si - fl;  // exact in binary32
-      const float u = uniform24(seed, (uint32_t)i, frame);
+      const float u = draw_u(us, seed, (uint32_t)i, frame);
       if (fl > 254.f) {
         status_or(st, APS_STATUS_COUNT_OVERFLOW);
         c = 255;
@@ -197,7 +199,8 @@ __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ s,
                                                  const int32_t* __restrict__ pixel_offset,
                                                  const float4* __restrict__ samples,
                                                  int64_t n_samples, int H, int W, int levels, int relaxed, float lam, float hfac,
-                                                 uint64_t seed, uint32_t frame, LevelPtrs Lp) {
+                                                 uint64_t seed, uint32_t frame, USource us,
+                                                 LevelPtrs Lp) {
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int x = blockIdx.x * 16 + tx, y = blockIdx.y * 16 + ty, n = blockIdx.z;
   __shared__ float4 tile[16][17];
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ s,
       float w = 1.f;
       if (relaxed) {
         const float p = si - fl;
-        const float u = uniform24(seed, (uint32_t)i, frame);
+        const float u = draw_u(us, seed, (uint32_t)i, frame);
         w = hfac * fminf(fmaxf(lam * (p - u) / p, 0.f), 1.f);
       }
       ax += w * r.x;
@@ -387,7 +390,8 @@ __global__ __launch_bounds__(256) void k_scatter_bwd(const float* __restrict__ s
                                                      const float4* __restrict__ samples,
                                                      int64_t n_samples, int N, int H, int W,
                                                      int levels, int relaxed, float lam, float hfac,
-                                                     uint64_t seed, uint32_t frame, GradLevels g,
+                                                     uint64_t seed, uint32_t frame, USource us,
+                                                     GradLevels g,
                                                      float* __restrict__ grad_s, int accumulate) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (size_t)N * H * W) return;
@@ -424,7 +428,7 @@ __global__ __launch_bounds__(256) void k_scatter_bwd(const float* __restrict__ s
       float w = 1.f;
       if (relaxed) {
         const float p = si - fl;
-        const float u = uniform24(seed, (uint32_t)i, frame);
+        const float u = draw_u(us, seed, (uint32_t)i, frame);
         const float t = lam * (p - u) / p;
         w = hfac * fminf(fmaxf(t, 0.f), 1.f);
         if (t > 0.f && t < 1.f) dwdp = hfac * lam * u / (p * p);
@@ -621,7 +625,16 @@ int aps_sample_mask(const float* s, int N, int H, int W, uint64_t seed, uint32_t
                     uint8_t* count, int32_t* pixel_offset, int32_t* sample_pixel,
                     int64_t capacity, int32_t* total, float* p_out, void* ws, size_t ws_bytes,
                     uint32_t* dev_status, void* stream) {
+  return aps_sample_mask_tex(s, N, H, W, seed, frame, nullptr, 0, count, pixel_offset,
+                             sample_pixel, capacity, total, p_out, ws, ws_bytes, dev_status, stream);
+}
+
+int aps_sample_mask_tex(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                        const float* u_tex, int tex_size, uint8_t* count, int32_t* pixel_offset,
+                        int32_t* sample_pixel, int64_t capacity, int32_t* total, float* p_out,
+                        void* ws, size_t ws_bytes, uint32_t* dev_status, void* stream) {
   if (N < 0 || H < 0 || W < 0 || capacity < 0) return APS_ERR_SHAPE;
+  if (u_tex && (tex_size < 1 || tex_size > kMaxTexSize)) return APS_ERR_ARG;
   const size_t npix = (size_t)N * H * W;
   if (npix > 0x7fffffffull) return APS_ERR_SHAPE;
   if (!total) return APS_ERR_NULL;
@@ -636,7 +649,8 @@ int aps_sample_mask(const float* s, int N, int H, int W, uint64_t seed, uint32_t
   const int nb = (int)((npix + kMaskBlock - 1) / kMaskBlock);
   int32_t* bsum = static_cast<int32_t*>(ws);
   int32_t* boff = bsum + nb;
-  k_mask_count<<<nb, kMaskBlock, 0, st>>>(s, (int)npix, seed, frame, count, p_out, bsum,
+  const USource us{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W};
+  k_mask_count<<<nb, kMaskBlock, 0, st>>>(s, (int)npix, seed, frame, us, count, p_out, bsum,
                                           dev_status);
   k_mask_scan<<<1, 1024, 0, st>>>(bsum, nb, boff, total);
   k_mask_compact<<<nb, kMaskBlock, 0, st>>>(count, (int)npix, boff, pixel_offset, sample_pixel,
@@ -665,7 +679,16 @@ int aps_scatter_samples(const float* s, const uint8_t* count, const int32_t* pix
                         int mode,
                         float lambda, uint64_t seed, uint32_t frame, float* const* L,
                         void* stream) {
+  return aps_scatter_samples_tex(s, count, pixel_offset, samples, n_samples, N, H, W, levels, mode,
+                                 lambda, seed, frame, nullptr, 0, L, stream);
+}
+
+int aps_scatter_samples_tex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                            const float* samples, int64_t n_samples, int N, int H, int W,
+                            int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
+                            const float* u_tex, int tex_size, float* const* L, void* stream) {
   if (n_samples < 0) return APS_ERR_SHAPE;
+  if (u_tex && (tex_size < 1 || tex_size > kMaxTexSize)) return APS_ERR_ARG;
   if (levels < 1 || levels > APS_MAX_LEVELS) return APS_ERR_UNSUPPORTED;
   if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
   if (mode != APS_HARD && mode != APS_RELAXED) return APS_ERR_ARG;
@@ -685,7 +708,8 @@ int aps_scatter_samples(const float* s, const uint8_t* count, const int32_t* pix
   k_scatter<<<grid, 256, 0, as_stream(stream)>>>(s, count, pixel_offset,
                                                  reinterpret_cast<const float4*>(samples),
                                                  n_samples, H, W, levels, mode == APS_RELAXED, lambda, hfac, seed,
-                                                 frame, lp);
+                                                 frame, USource{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W},
+                                                 lp);
   APS_LAUNCH_CHECK();
   return APS_OK;
 }
@@ -730,7 +754,18 @@ int aps_scatter_samples_bwd(const float* s, const uint8_t* count, const int32_t*
                             int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
                             const float* const* grad_L, float* grad_s, int accumulate,
                             void* stream) {
+  return aps_scatter_samples_bwd_tex(s, count, pixel_offset, samples, n_samples, N, H, W, levels,
+                                     mode, lambda, seed, frame, nullptr, 0, grad_L, grad_s,
+                                     accumulate, stream);
+}
+
+int aps_scatter_samples_bwd_tex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                                const float* samples, int64_t n_samples, int N, int H, int W,
+                                int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
+                                const float* u_tex, int tex_size, const float* const* grad_L,
+                                float* grad_s, int accumulate, void* stream) {
   if (n_samples < 0) return APS_ERR_SHAPE;
+  if (u_tex && (tex_size < 1 || tex_size > kMaxTexSize)) return APS_ERR_ARG;
   if (levels < 1 || levels > APS_MAX_LEVELS) return APS_ERR_UNSUPPORTED;
   if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
   if (mode != APS_HARD && mode != APS_RELAXED) return APS_ERR_ARG;
@@ -750,7 +785,8 @@ int aps_scatter_samples_bwd(const float* s, const uint8_t* count, const int32_t*
   const float hfac = 2.f * lambda / (2.f * lambda - 1.f);
   k_scatter_bwd<<<(unsigned)((npix + 255) / 256), 256, 0, as_stream(stream)>>>(
       s, count, pixel_offset, reinterpret_cast<const float4*>(samples), n_samples, N, H, W, levels,
-      mode == APS_RELAXED, lambda, hfac, seed, frame, g, grad_s, accumulate);
+      mode == APS_RELAXED, lambda, hfac, seed, frame,
+      USource{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W}, g, grad_s, accumulate);
   APS_LAUNCH_CHECK();
   return APS_OK;
 }

@@ -85,7 +85,18 @@ def normalize_density(z, budget: float, uniform_frac: float = 1.0 / 8.0, status=
 
 # ------------------------------------------------------------------ mask (a3)
 
-def sample_mask(s, seed: int, frame: int, capacity: int | None = None, want_p=False, status=None):
+def _tex(u_tex):
+    """(pointer, side) of an optional square float32 device texture of thresholds."""
+    if u_tex is None:
+        return None, 0
+    _need(u_tex, "u_tex", _F32)
+    if u_tex.dim() != 2 or u_tex.shape[0] != u_tex.shape[1]:
+        raise ValueError("u_tex must be a square [T, T] float32 texture")
+    return _p(u_tex), u_tex.shape[0]
+
+
+def sample_mask(s, seed: int, frame: int, capacity: int | None = None, want_p=False, status=None,
+                u_tex=None):
     _need(s, "s", _F32)
     N, H, W = s.shape
     dev = s.device
@@ -100,8 +111,10 @@ def sample_mask(s, seed: int, frame: int, capacity: int | None = None, want_p=Fa
     lib = L.load()
     nb = lib.aps_sample_mask_workspace_size(N, H, W)
     ws = WS.get(nb, dev)
-    L.check(lib.aps_sample_mask(_p(s), N, H, W, seed, frame, _p(count), _p(poff), _p(spix),
-                                capacity, _p(total), _p(p), _p(ws), nb, _p(status), _stream()),
+    tp, T = _tex(u_tex)
+    L.check(lib.aps_sample_mask_tex(_p(s), N, H, W, seed, frame, tp, T, _p(count), _p(poff),
+                                    _p(spix), capacity, _p(total), _p(p), _p(ws), nb, _p(status),
+                                    _stream()),
             "sample_mask")
     return dict(count=count, pixel_offset=poff, sample_pixel=spix, total=total, p=p,
                 capacity=capacity)
@@ -120,16 +133,17 @@ def fixture_render(pool, count, pixel_offset, capacity: int):
 # ------------------------------------------------------------------ scatter (a4)
 
 def scatter_samples(s, count, pixel_offset, samples, levels: int, mode: str = "hard",
-                    lam: float = 10.0, seed: int = 0, frame: int = 0):
+                    lam: float = 10.0, seed: int = 0, frame: int = 0, u_tex=None):
     _need(s, "s", _F32)
     _need(samples, "samples", _F32)
     N, H, W = s.shape
     Ls = [torch.empty((N, H >> l, W >> l, 4), dtype=_F32, device=s.device) for l in range(levels)]
     arr = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in Ls])
     m = L.APS_HARD if mode == "hard" else L.APS_RELAXED
-    L.check(L.load().aps_scatter_samples(_p(s), _p(count), _p(pixel_offset), _p(samples),
-                                         samples.shape[0], N, H, W, levels, m, lam, seed, frame,
-                                         arr, _stream()),
+    tp, T = _tex(u_tex)
+    L.check(L.load().aps_scatter_samples_tex(_p(s), _p(count), _p(pixel_offset), _p(samples),
+                                             samples.shape[0], N, H, W, levels, m, lam, seed, frame,
+                                             tp, T, arr, _stream()),
             "scatter_samples")
     return Ls
 
@@ -341,7 +355,7 @@ def denoise_pyramid_bwd(Ls, logits, KD: int, KU: int, KT: int, prev, mv, grad_ou
 
 
 def scatter_samples_bwd(s, count, pixel_offset, samples, grad_L, mode="relaxed", lam=10.0,
-                        seed=0, frame=0, grad_s=None):
+                        seed=0, frame=0, grad_s=None, u_tex=None):
     _need(s, "s", _F32)
     N, H, W = s.shape
     acc = grad_s is not None
@@ -349,9 +363,11 @@ def scatter_samples_bwd(s, count, pixel_offset, samples, grad_L, mode="relaxed",
         grad_s = torch.empty_like(s)
     arr = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in grad_L])
     m = L.APS_HARD if mode == "hard" else L.APS_RELAXED
-    L.check(L.load().aps_scatter_samples_bwd(_p(s), _p(count), _p(pixel_offset), _p(samples),
-                                             samples.shape[0], N, H, W, len(grad_L), m, lam, seed,
-                                             frame, arr, _p(grad_s), int(acc), _stream()),
+    tp, T = _tex(u_tex)
+    L.check(L.load().aps_scatter_samples_bwd_tex(_p(s), _p(count), _p(pixel_offset), _p(samples),
+                                                 samples.shape[0], N, H, W, len(grad_L), m, lam,
+                                                 seed, frame, tp, T, arr, _p(grad_s), int(acc),
+                                                 _stream()),
             "scatter_samples_bwd")
     return grad_s
 

@@ -32,6 +32,7 @@ class FrameConfig:
     uniform_frac: float = 1.0 / 8.0   # Sec. 3: 1/8 of the budget spread uniformly
     kernel_net: str = "unet"          # "unet" or "cnn3" (single-level 3-layer CNN)
     density_scale: int = 1            # 2: sampler at a quarter of the pixels (Sec. 7)
+    u_noise: str = "philox"           # u of the mask: "philox" or "blue" (void-and-cluster texture)
 
     @property
     def sampler_cin(self) -> int:
@@ -65,7 +66,8 @@ CONFIGS = {
     # the paper's own reconstruction (App. A): 5 levels, kd 5x5 everywhere, literal 2x2 ku,
     # kt 5x5 (54-way softmax at level 0), with the quarter-resolution density map of Sec. 7;
     # 1080 rows are not divisible by 2^4, so the frame is 1080p padded to 1088 rows
-    "paper": FrameConfig("paper", 1088, 1920, 0.25, 5, 5, 2, 5, True, BF16, BF16, density_scale=2),
+    "paper": FrameConfig("paper", 1088, 1920, 0.25, 5, 5, 2, 5, True, BF16, BF16, density_scale=2,
+                         u_noise="blue"),
 }
 
 
@@ -100,6 +102,12 @@ class FrameRenderer:
         if kernel_weights is not None:
             self.knet = ops.Net(kernel_spec(cfg), kernel_weights, cfg.net_dtype, self.device)
         self._const_logits = None
+        self.u_tex = None
+        if cfg.u_noise == "blue":   # a 64x64 void-and-cluster threshold texture (Sec. 6.3)
+            import procgen
+            self.u_tex = torch.tensor(procgen.blue_noise_thresholds(64), device=self.device)
+        elif cfg.u_noise != "philox":
+            raise ValueError(cfg.u_noise)
 
     # -- stage 1: density ------------------------------------------------------------
     def density(self, aux, prev=None, mv=None):
@@ -120,7 +128,7 @@ class FrameRenderer:
     def request(self, s, seed: int, frame: int):
         N = s.shape[0]
         cap = int(N * self.cfg.H * self.cfg.W * (self.cfg.budget + 1.0)) + 1024
-        return ops.sample_mask(s, seed, frame, capacity=cap)
+        return ops.sample_mask(s, seed, frame, capacity=cap, u_tex=self.u_tex)
 
     # -- stage 3: reconstruction -----------------------------------------------------------
     def logits(self, aux, L0, s, prev=None, mv=None):
@@ -148,7 +156,7 @@ class FrameRenderer:
                     mode="hard", lam=10.0):
         cfg = self.cfg
         Ls = ops.scatter_samples(s, req["count"], req["pixel_offset"], samples, cfg.levels, mode,
-                                 lam, seed, frame)
+                                 lam, seed, frame, u_tex=self.u_tex)
         use_prev = prev if cfg.temporal else None
         use_mv = mv if cfg.temporal else None
         z = self.logits(aux, Ls[0], s, use_prev, use_mv)

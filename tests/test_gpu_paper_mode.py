@@ -159,8 +159,8 @@ def test_scatter_five_levels(ops, mode):
 
 def test_paper_mode_frame(ops):
     """One temporal frame of the paper configuration (reduced to 64x96), random-init networks:
-    quarter-resolution density, mask, render stand-in, scatter into 5 levels, five-head U-Net,
-    5-level 5/2/5 pyramid with the warped previous output."""
+    quarter-resolution density, blue-noise mask, render stand-in, scatter into 5 levels,
+    five-head U-Net, 5-level 5/2/5 pyramid with the warped previous output."""
     from paper_2602_08642_amd import pipeline
     cfg = dataclasses.replace(pipeline.CONFIGS["paper"], H=64, W=96)
     assert cfg.head_channels() == [54, 29, 29, 29, 25]
@@ -188,13 +188,16 @@ def test_paper_mode_frame(ops):
     assert abs(float(s.double().sum()) - cfg.H * cfg.W * cfg.budget) < 1e-3
     # mask (bit-exact on the GPU's s) and the render stand-in
     req = r.request(s, seed, t)
-    mo = osamp.mask(s.cpu().numpy(), seed, t)
+    assert r.u_tex is not None                        # the paper configuration dithers with blue noise
+    tex = r.u_tex.cpu().numpy()
+    assert np.array_equal(tex, procgen.blue_noise_thresholds(64))
+    mo = osamp.mask(s.cpu().numpy(), seed, t, u_tex=tex)
     assert np.array_equal(req["count"].cpu().numpy(), mo["count"])
     pool = torch.tensor(procgen.sample_pool(fr.truth, seed, t, 8), device=DEV)
     smp = ops.fixture_render(pool, req["count"], req["pixel_offset"], req["capacity"])
     out, Ls, logits = r.reconstruct(aux, s, req, smp, seed, t, prev, mv)
     total = int(req["total"].item())
-    L0r = osamp.scatter(s.double().cpu(), mo["count"], smp[:total].cpu().numpy(), seed, t)
+    L0r = osamp.scatter(s.double().cpu(), mo["count"], smp[:total].cpu().numpy(), seed, t, u_tex=tex)
     for l, ref in enumerate(osamp.pyramid(L0r, cfg.levels)):
         assert torch.allclose(Ls[l].double().cpu(), ref, rtol=1e-5, atol=1e-5), l
     # five-head U-Net on the GPU's features
