@@ -37,7 +37,14 @@ enum aps_status {
 };
 
 enum aps_dtype { APS_F32 = 0, APS_BF16 = 1 };
-enum aps_mode { APS_HARD = 0, APS_RELAXED = 1 };
+enum aps_mode {
+  APS_HARD = 0,
+  APS_RELAXED = 1,
+  APS_STRAIGHT_THROUGH = 2, /* compared estimators (Sec. 4.1, 4.3): see aps_scatter_samples_ex */
+  APS_GUMBEL = 3,
+  APS_DASR = 4
+};
+enum aps_rounding { APS_ROUND_STOCHASTIC = 0, APS_ROUND_HOLDOUT = 1, APS_ROUND_DETERMINISTIC = 2 };
 enum aps_feature_kind { APS_FEAT_SAMPLER = 0, APS_FEAT_KERNEL = 1 };
 enum aps_conv_mode { APS_CONV_DIRECT = 0, APS_CONV_POOL2 = 1, APS_CONV_UP2_CAT = 2 };
 
@@ -153,17 +160,22 @@ int aps_sample_mask(const float* s, int N, int H, int W, uint64_t seed, uint32_t
                     int64_t capacity, int32_t* total, float* p_out, void* ws, size_t ws_bytes,
                     uint32_t* dev_status, void* stream);
 
-/* The same mask with u from a blue-noise threshold texture (Sec. 6.3 dithers with blue noise):
- * u_tex float32 [tex_size][tex_size] on the device (e.g. void-and-cluster thresholds
- * (rank + 1/2) / tex_size^2), tiled over each image with a toroidal offset per image and frame,
- * (ox, oy) = (word0, word1) mod tex_size of Philox4x32-10(key = seed, counter = (n, frame, 2, 0)):
- * u[n][y][x] = u_tex[(y + oy) mod T][(x + ox) mod T].  u_tex == NULL gives the Philox u above.
- * APS_ERR_ARG when u_tex is given and tex_size is outside 1..4096.  The caller keeps u_tex
- * alive until the work on the stream has finished. */
-int aps_sample_mask_tex(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
-                        const float* u_tex, int tex_size, uint8_t* count, int32_t* pixel_offset,
-                        int32_t* sample_pixel, int64_t capacity, int32_t* total, float* p_out,
-                        void* ws, size_t ws_bytes, uint32_t* dev_status, void* stream);
+/* The mask with two options.  u: from a blue-noise threshold texture (Sec. 6.3 dithers with
+ * blue noise): u_tex float32 [tex_size][tex_size] on the device (e.g. void-and-cluster
+ * thresholds (rank + 1/2) / tex_size^2), tiled over each image with a toroidal offset per image
+ * and frame, (ox, oy) = (word0, word1) mod tex_size of Philox4x32-10(key = seed,
+ * counter = (n, frame, 2, 0)): u[n][y][x] = u_tex[(y + oy) mod T][(x + ox) mod T]; u_tex == NULL
+ * gives the Philox u above.  rounding: APS_ROUND_STOCHASTIC count = floor(s) + [u < p] (as
+ * above); APS_ROUND_HOLDOUT count = floor(s) + [p > 0], the holdout requested for every pixel
+ * with p > 0 (what the straight-through and Gumbel-Softmax scatter modes read);
+ * APS_ROUND_DETERMINISTIC count = round(s) = floor(s) + [p >= 1/2] (Sec. 4.1 eq. kuz_fw, the
+ * DASR mode).  APS_ERR_ARG for tex_size outside 1..4096 with a texture, or another rounding.
+ * The caller keeps u_tex alive until the work on the stream has finished. */
+int aps_sample_mask_ex(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                       const float* u_tex, int tex_size, int rounding, uint8_t* count,
+                       int32_t* pixel_offset, int32_t* sample_pixel, int64_t capacity,
+                       int32_t* total, float* p_out, void* ws, size_t ws_bytes,
+                       uint32_t* dev_status, void* stream);
 
 /* Renderer stand-in (not part of the method): writes sample j of pixel i as
  * pool[i][j mod J] (pool float32 [N*H*W][J][4]) at samples[pixel_offset[i] + j]. */
@@ -187,12 +199,20 @@ int aps_scatter_samples(const float* s, const uint8_t* count, const int32_t* pix
                         int mode,
                         float lambda, uint64_t seed, uint32_t frame, float* const* L,
                         void* stream);
-/* aps_scatter_samples with the relaxed holdout's u from a blue-noise texture, as
- * aps_sample_mask_tex (pass the texture the mask was drawn with). */
-int aps_scatter_samples_tex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
-                            const float* samples, int64_t n_samples, int N, int H, int W,
-                            int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
-                            const float* u_tex, int tex_size, float* const* L, void* stream);
+/* aps_scatter_samples with more modes and the optional u texture of aps_sample_mask_ex (pass
+ * the texture the mask was drawn with).  The holdout (sample floor(s) of the pixel, when
+ * requested) enters with weight w:
+ *   APS_HARD, APS_RELAXED: as above (param = lambda >= 1 for RELAXED); APS_ROUND_STOCHASTIC masks;
+ *   APS_STRAIGHT_THROUGH: w = [u < p] (the hard forward; its backward takes dw/dp = 1);
+ *   APS_GUMBEL: w = sigmoid((logit p - logit u) / tau), tau = param > 0 (the binary
+ *     Gumbel-Softmax relaxation the paper contrasts with its ramp, Sec. 4.3);
+ *   both with APS_ROUND_HOLDOUT masks, so the holdout of every pixel with p > 0 is present;
+ *   APS_DASR (Sec. 4.1 eq. kuz_fw): L0 = mean of the count requested samples (0 for count 0),
+ *     with APS_ROUND_DETERMINISTIC masks. */
+int aps_scatter_samples_ex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                           const float* samples, int64_t n_samples, int N, int H, int W,
+                           int levels, int mode, float param, uint64_t seed, uint32_t frame,
+                           const float* u_tex, int tex_size, float* const* L, void* stream);
 
 /* Network inputs (C <= 16 channels, zero padded), out [N,H,W,C] in out_dtype.
  *   APS_FEAT_SAMPLER: aux[0..6], then with prev: tonemap(W prev) RGB, valid
@@ -282,12 +302,17 @@ int aps_scatter_samples_bwd(const float* s, const uint8_t* count, const int32_t*
                             int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
                             const float* const* grad_L, float* grad_s, int accumulate,
                             void* stream);
-/* aps_scatter_samples_bwd with u from a blue-noise texture, as aps_sample_mask_tex. */
-int aps_scatter_samples_bwd_tex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
-                                const float* samples, int64_t n_samples, int N, int H, int W,
-                                int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
-                                const float* u_tex, int tex_size, const float* const* grad_L,
-                                float* grad_s, int accumulate, void* stream);
+/* aps_scatter_samples_bwd for the modes of aps_scatter_samples_ex: dL0/ds = -L0/s + (r/s) dw/dp
+ * with dw/dp = 1 (straight-through), w (1 - w) / (tau p (1 - p)) (Gumbel-Softmax), the ramp's
+ * slope (relaxed), 0 (hard); APS_DASR the surrogate of Sec. 4.1 eq. kuz_grad,
+ * dL0/ds = (L_ref - L0) / round(s) for s >= 1/2 and L_ref below, L_ref float32 RGBA [N,H,W]
+ * (the reference radiance; required for APS_DASR, ignored otherwise). */
+int aps_scatter_samples_bwd_ex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                               const float* samples, int64_t n_samples, int N, int H, int W,
+                               int levels, int mode, float param, uint64_t seed, uint32_t frame,
+                               const float* u_tex, int tex_size, const float* L_ref,
+                               const float* const* grad_L, float* grad_s, int accumulate,
+                               void* stream);
 
 /* Budget normalisation backward (Sec. 3): grad_z (written) = c1 sm (g - sum(sm g)) per frame,
  * c1 = (1-f) B Npx; fixed-tree reductions (deterministic). */

@@ -57,8 +57,11 @@ def u_values(N, H, W, seed: int, frame: int, u_tex=None):
     return u
 
 
-def mask(s32, seed: int, frame: int, u_tex=None):
+def mask(s32, seed: int, frame: int, u_tex=None, rounding: str = "stochastic"):
     """s32: float32 [N, H, W] densities; u_tex: optional float32 [T, T] threshold texture.
+    rounding: "stochastic" count = floor(s) + [u < p] (eq. holdout); "holdout" floor(s) + [p > 0]
+    (the holdout requested wherever it exists, for the straight-through and Gumbel-Softmax
+    estimators); "deterministic" round(s) = floor(s + 1/2) (Sec. 4.1 eq. kuz_fw, DASR).
 
     Returns dict(count uint8 [N,H,W], p float64 [N,H,W] (exact), u float64, take bool,
     block_offset int64 [ceil(Npix/256)+1] (exclusive; last entry = total),
@@ -69,7 +72,14 @@ def mask(s32, seed: int, frame: int, u_tex=None):
     fl = np.floor(s)
     p = s - fl                                                 # exact
     u = u_values(N, H, W, seed, frame, u_tex)
-    take = u < p
+    if rounding == "stochastic":
+        take = u < p
+    elif rounding == "holdout":
+        take = p > 0
+    elif rounding == "deterministic":
+        take = np.floor(s + 0.5) > fl
+    else:
+        raise ValueError(rounding)
     cnt = fl + take
     overflow = bool((cnt > COUNT_MAX).any())
     count = np.minimum(cnt, COUNT_MAX).astype(np.int64)

@@ -7,7 +7,8 @@ LIB_PATH = os.path.join(_HERE, "libaps.so")
 
 APS_OK, APS_ERR_NULL, APS_ERR_SHAPE, APS_ERR_UNSUPPORTED, APS_ERR_WORKSPACE, APS_ERR_HIP, APS_ERR_ARG = range(7)
 APS_F32, APS_BF16 = 0, 1
-APS_HARD, APS_RELAXED = 0, 1
+APS_HARD, APS_RELAXED, APS_STRAIGHT_THROUGH, APS_GUMBEL, APS_DASR = range(5)
+APS_ROUND_STOCHASTIC, APS_ROUND_HOLDOUT, APS_ROUND_DETERMINISTIC = range(3)
 APS_FEAT_SAMPLER, APS_FEAT_KERNEL = 0, 1
 APS_CONV_DIRECT, APS_CONV_POOL2, APS_CONV_UP2_CAT = 0, 1, 2
 APS_MAX_LEVELS = 5
@@ -44,10 +45,10 @@ SIGNATURES = {
     "aps_upsample_nearest2": (I, [P, I, I, I, P, P]),
     "aps_sample_mask_workspace_size": (SZ, [I, I, I]),
     "aps_sample_mask": (I, [P, I, I, I, U64, U32, P, P, P, I64, P, P, P, SZ, P, P]),
-    "aps_sample_mask_tex": (I, [P, I, I, I, U64, U32, P, I, P, P, P, I64, P, P, P, SZ, P, P]),
+    "aps_sample_mask_ex": (I, [P, I, I, I, U64, U32, P, I, I, P, P, P, I64, P, P, P, SZ, P, P]),
     "aps_fixture_render": (I, [P, I, P, P, I, I, I, I64, P, P]),
     "aps_scatter_samples": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P]),
-    "aps_scatter_samples_tex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P]),
+    "aps_scatter_samples_ex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P]),
     "aps_assemble_features": (I, [I, P, P, P, P, P, I, I, I, I, I, P, P]),
     "aps_kernel_predict_workspace_size": (SZ, [C.POINTER(NetDesc), I, I, I]),
     "aps_kernel_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, I, P, I, P, P, SZ, P]),
@@ -60,7 +61,7 @@ SIGNATURES = {
     "aps_denoise_pyramid_bwd": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, P, P, I, P, P, P, P,
                                     SZ, P]),
     "aps_scatter_samples_bwd": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P, I, P]),
-    "aps_scatter_samples_bwd_tex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P, I, P]),
+    "aps_scatter_samples_bwd_ex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P, P, I, P]),
     "aps_normalize_bwd_workspace_size": (SZ, [I, I, I]),
     "aps_normalize_density_bwd": (I, [P, I, I, I, F, F, P, P, P, SZ, P]),
     "aps_assemble_features_bwd": (I, [I, P, P, P, I, I, I, I, I, P, P, P, P, P]),

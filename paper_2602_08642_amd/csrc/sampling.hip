@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_norm_apply(const float* __restrict__ z,
 // ------------------------------------------------------------------ sample mask
 __global__ __launch_bounds__(kMaskBlock) void k_mask_count(const float* __restrict__ s,
                                                            int npix, uint64_t seed, uint32_t frame,
-                                                           USource us,
+                                                           USource us, int rounding,
                                                            uint8_t* __restrict__ count,
                                                            float* __restrict__ p_out,
                                                            int32_t* __restrict__ block_sum,
@@ -101,12 +101,17 @@ __global__ __launch_bounds__(kMaskBlock) void k_mask_count(const float* __restri
     } else {
       const float fl = floorf(si);
       p = si - fl;  // exact in binary32
-      const float u = draw_u(us, seed, (uint32_t)i, frame);
+      // stochastic: floor(s) + [u < p] (eq. holdout); holdout always requested: floor(s) + [p > 0]
+      // (straight-through, Gumbel-Softmax); deterministic: round(s) (Sec. 4.1 eq. kuz_fw)
+      int extra;
+      if (rounding == APS_ROUND_STOCHASTIC) extra = draw_u(us, seed, (uint32_t)i, frame) < p ? 1 : 0;
+      else if (rounding == APS_ROUND_HOLDOUT) extra = p > 0.f ? 1 : 0;
+      else extra = p >= 0.5f ? 1 : 0;
       if (fl > 254.f) {
         status_or(st, APS_STATUS_COUNT_OVERFLOW);
         c = 255;
       } else {
-        c = (int)fl + (u < p ? 1 : 0);
+        c = (int)fl + extra;
         if (c > 255) {
           status_or(st, APS_STATUS_COUNT_OVERFLOW);
           c = 255;
@@ -193,12 +198,37 @@ __global__ __launch_bounds__(256) void k_fixture_render(const float4* __restrict
 
 // ------------------------------------------------------------------ scatter + pyramid
 // One 16x16 tile of level-0 pixels per block.  Level 0 is the s-normalised estimate,
+// Weight w of the holdout sample and dw/dp (p = s - floor(s)) for each scatter mode:
+//   hard: w = 1 when the holdout was requested, no gradient through the indicator;
+//   relaxed (Sec. 4.3, eqs. relaxed_holdout, h_factor; u mirrored): w = h clamp(lam (p - u)/p);
+//   straight-through: w = [u < p], dw/dp taken as 1;
+//   Gumbel-Softmax (binary concrete, temperature tau = param): w = sigmoid((logit p - logit u)/tau).
+struct HoldW {
+  float w, dwdp;
+};
+__device__ inline HoldW holdout_weight(int mode, float p, float u, float param, float hfac) {
+  HoldW h{1.f, 0.f};
+  if (mode == APS_RELAXED) {
+    const float t = param * (p - u) / p;
+    h.w = hfac * fminf(fmaxf(t, 0.f), 1.f);
+    if (t > 0.f && t < 1.f) h.dwdp = hfac * param * u / (p * p);
+  } else if (mode == APS_STRAIGHT_THROUGH) {
+    h.w = u < p ? 1.f : 0.f;
+    h.dwdp = 1.f;
+  } else if (mode == APS_GUMBEL) {
+    const float z = ((logf(p) - log1pf(-p)) - (logf(u) - log1pf(-u))) / param;
+    h.w = 1.f / (1.f + expf(-z));
+    h.dwdp = h.w * (1.f - h.w) / (param * p * (1.f - p));
+  }
+  return h;
+}
+
 // levels 1.. are 2x2 means of the level above, reduced in LDS (= 2^l x 2^l block means).
 __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ s,
                                                  const uint8_t* __restrict__ count,
                                                  const int32_t* __restrict__ pixel_offset,
                                                  const float4* __restrict__ samples,
-                                                 int64_t n_samples, int H, int W, int levels, int relaxed, float lam, float hfac,
+                                                 int64_t n_samples, int H, int W, int levels, int mode, float lam, float hfac,
                                                  uint64_t seed, uint32_t frame, USource us,
                                                  LevelPtrs Lp) {
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -216,25 +246,31 @@ __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ s,
     // samples past the caller's buffer (a mask that overflowed its capacity) read as 0
     const int lim = (int)min((int64_t)c, max((int64_t)0, n_samples - off));
     float ax = 0.f, ay = 0.f, az = 0.f;
-    for (int j = 0; j < min(nb, lim); ++j) {
-      const float4 v = samples[off + j];
-      ax += v.x;
-      ay += v.y;
-      az += v.z;
-    }
-    if (c > nb && nb < lim) {  // the holdout sample was taken (u < p)
-      const float4 r = samples[off + nb];
-      float w = 1.f;
-      if (relaxed) {
-        const float p = si - fl;
-        const float u = draw_u(us, seed, (uint32_t)i, frame);
-        w = hfac * fminf(fmaxf(lam * (p - u) / p, 0.f), 1.f);
+    if (mode == APS_DASR) {  // Sec. 4.1 eq. kuz_fw: the mean of the round(s) requested samples
+      for (int j = 0; j < lim; ++j) {
+        const float4 v = samples[off + j];
+        ax += v.x;
+        ay += v.y;
+        az += v.z;
       }
-      ax += w * r.x;
-      ay += w * r.y;
-      az += w * r.z;
+      if (c > 0) L = make_float4(ax / (float)c, ay / (float)c, az / (float)c, 0.f);
+    } else {
+      for (int j = 0; j < min(nb, lim); ++j) {
+        const float4 v = samples[off + j];
+        ax += v.x;
+        ay += v.y;
+        az += v.z;
+      }
+      if (c > nb && nb < lim) {  // the holdout sample was requested
+        const float4 r = samples[off + nb];
+        const float u = mode == APS_HARD ? 0.f : draw_u(us, seed, (uint32_t)i, frame);
+        const float w = holdout_weight(mode, si - fl, u, lam, hfac).w;
+        ax += w * r.x;
+        ay += w * r.y;
+        az += w * r.z;
+      }
+      if (si > 0.f) L = make_float4(ax / si, ay / si, az / si, 0.f);
     }
-    if (si > 0.f) L = make_float4(ax / si, ay / si, az / si, 0.f);
     Lp.p[0][i] = L;
   }
   tile[ty][tx] = L;
@@ -376,10 +412,10 @@ __global__ __launch_bounds__(256) void k_features(int kind, const float* __restr
 
 // ======================================================================== backward
 // ------------------------------------------------------------------ scatter + pyramid
-// L0 = (base + w r) / s with w = 1 (hard) or h * clamp(lambda (p - u) / p, 0, 1) (relaxed),
-// p = s - floor(s):  dL0/ds = -L0 / s + (r / s) dw/dp,  dw/dp = h lambda u / p^2 inside the
-// ramp and 0 on its clamped parts and in hard mode.  The pyramid levels are block means of L0,
-// so dLoss/dL0 collects dLoss/dL^l / 4^l from every ancestor.
+// L0 = (base + w r) / s with the holdout weight w of the mode (holdout_weight), p = s - floor(s):
+// dL0/ds = -L0 / s + (r / s) dw/dp.  DASR (Sec. 4.1 eq. kuz_grad): the surrogate
+// dL0/ds = (L_ref - L0) / round(s) for s >= 1/2 and L_ref below.  The pyramid levels are block
+// means of L0, so dLoss/dL0 collects dLoss/dL^l / 4^l from every ancestor.
 struct GradLevels {
   const float4* p[APS_MAX_LEVELS];
 };
@@ -389,9 +425,9 @@ __global__ __launch_bounds__(256) void k_scatter_bwd(const float* __restrict__ s
                                                      const int32_t* __restrict__ pixel_offset,
                                                      const float4* __restrict__ samples,
                                                      int64_t n_samples, int N, int H, int W,
-                                                     int levels, int relaxed, float lam, float hfac,
+                                                     int levels, int mode, float lam, float hfac,
                                                      uint64_t seed, uint32_t frame, USource us,
-                                                     GradLevels g,
+                                                     const float4* __restrict__ Lref, GradLevels g,
                                                      float* __restrict__ grad_s, int accumulate) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (size_t)N * H * W) return;
@@ -408,7 +444,26 @@ __global__ __launch_bounds__(256) void k_scatter_bwd(const float* __restrict__ s
   }
   const float si = s[i];
   float out = 0.f;
-  if (si > 0.f) {
+  if (mode == APS_DASR) {
+    const int c = count[i];
+    const int off = pixel_offset[i];
+    const int lim = (int)min((int64_t)c, max((int64_t)0, n_samples - off));
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    for (int j = 0; j < lim; ++j) {
+      const float4 v = samples[off + j];
+      ax += v.x;
+      ay += v.y;
+      az += v.z;
+    }
+    const float4 lr = Lref[i];
+    if (si >= 0.5f && c > 0) {
+      const float inv = 1.f / (float)c;
+      out = ge.x * (lr.x - ax * inv) * inv + ge.y * (lr.y - ay * inv) * inv +
+            ge.z * (lr.z - az * inv) * inv;
+    } else {
+      out = ge.x * lr.x + ge.y * lr.y + ge.z * lr.z;
+    }
+  } else if (si > 0.f) {
     const int c = count[i];
     const int off = pixel_offset[i];
     const float fl = floorf(si);
@@ -425,17 +480,12 @@ __global__ __launch_bounds__(256) void k_scatter_bwd(const float* __restrict__ s
     float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
     if (c > nb && nb < lim) {
       r = samples[off + nb];
-      float w = 1.f;
-      if (relaxed) {
-        const float p = si - fl;
-        const float u = draw_u(us, seed, (uint32_t)i, frame);
-        const float t = lam * (p - u) / p;
-        w = hfac * fminf(fmaxf(t, 0.f), 1.f);
-        if (t > 0.f && t < 1.f) dwdp = hfac * lam * u / (p * p);
-      }
-      ax += w * r.x;
-      ay += w * r.y;
-      az += w * r.z;
+      const float u = mode == APS_HARD ? 0.f : draw_u(us, seed, (uint32_t)i, frame);
+      const HoldW h = holdout_weight(mode, si - fl, u, lam, hfac);
+      dwdp = h.dwdp;
+      ax += h.w * r.x;
+      ay += h.w * r.y;
+      az += h.w * r.z;
     }
     const float inv = 1.f / si;
     const float lx = ax * inv, ly = ay * inv, lz = az * inv;
@@ -625,16 +675,21 @@ int aps_sample_mask(const float* s, int N, int H, int W, uint64_t seed, uint32_t
                     uint8_t* count, int32_t* pixel_offset, int32_t* sample_pixel,
                     int64_t capacity, int32_t* total, float* p_out, void* ws, size_t ws_bytes,
                     uint32_t* dev_status, void* stream) {
-  return aps_sample_mask_tex(s, N, H, W, seed, frame, nullptr, 0, count, pixel_offset,
-                             sample_pixel, capacity, total, p_out, ws, ws_bytes, dev_status, stream);
+  return aps_sample_mask_ex(s, N, H, W, seed, frame, nullptr, 0, APS_ROUND_STOCHASTIC, count,
+                            pixel_offset, sample_pixel, capacity, total, p_out, ws, ws_bytes,
+                            dev_status, stream);
 }
 
-int aps_sample_mask_tex(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
-                        const float* u_tex, int tex_size, uint8_t* count, int32_t* pixel_offset,
-                        int32_t* sample_pixel, int64_t capacity, int32_t* total, float* p_out,
-                        void* ws, size_t ws_bytes, uint32_t* dev_status, void* stream) {
+int aps_sample_mask_ex(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                       const float* u_tex, int tex_size, int rounding, uint8_t* count,
+                       int32_t* pixel_offset, int32_t* sample_pixel, int64_t capacity,
+                       int32_t* total, float* p_out, void* ws, size_t ws_bytes,
+                       uint32_t* dev_status, void* stream) {
   if (N < 0 || H < 0 || W < 0 || capacity < 0) return APS_ERR_SHAPE;
   if (u_tex && (tex_size < 1 || tex_size > kMaxTexSize)) return APS_ERR_ARG;
+  if (rounding != APS_ROUND_STOCHASTIC && rounding != APS_ROUND_HOLDOUT &&
+      rounding != APS_ROUND_DETERMINISTIC)
+    return APS_ERR_ARG;
   const size_t npix = (size_t)N * H * W;
   if (npix > 0x7fffffffull) return APS_ERR_SHAPE;
   if (!total) return APS_ERR_NULL;
@@ -650,8 +705,8 @@ int aps_sample_mask_tex(const float* s, int N, int H, int W, uint64_t seed, uint
   int32_t* bsum = static_cast<int32_t*>(ws);
   int32_t* boff = bsum + nb;
   const USource us{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W};
-  k_mask_count<<<nb, kMaskBlock, 0, st>>>(s, (int)npix, seed, frame, us, count, p_out, bsum,
-                                          dev_status);
+  k_mask_count<<<nb, kMaskBlock, 0, st>>>(s, (int)npix, seed, frame, us, rounding, count, p_out,
+                                          bsum, dev_status);
   k_mask_scan<<<1, 1024, 0, st>>>(bsum, nb, boff, total);
   k_mask_compact<<<nb, kMaskBlock, 0, st>>>(count, (int)npix, boff, pixel_offset, sample_pixel,
                                             capacity, dev_status);
@@ -679,20 +734,23 @@ int aps_scatter_samples(const float* s, const uint8_t* count, const int32_t* pix
                         int mode,
                         float lambda, uint64_t seed, uint32_t frame, float* const* L,
                         void* stream) {
-  return aps_scatter_samples_tex(s, count, pixel_offset, samples, n_samples, N, H, W, levels, mode,
-                                 lambda, seed, frame, nullptr, 0, L, stream);
+  if (mode != APS_HARD && mode != APS_RELAXED) return APS_ERR_ARG;
+  return aps_scatter_samples_ex(s, count, pixel_offset, samples, n_samples, N, H, W, levels, mode,
+                                lambda, seed, frame, nullptr, 0, L, stream);
 }
 
-int aps_scatter_samples_tex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
-                            const float* samples, int64_t n_samples, int N, int H, int W,
-                            int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
-                            const float* u_tex, int tex_size, float* const* L, void* stream) {
+int aps_scatter_samples_ex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                           const float* samples, int64_t n_samples, int N, int H, int W,
+                           int levels, int mode, float param, uint64_t seed, uint32_t frame,
+                           const float* u_tex, int tex_size, float* const* L, void* stream) {
+  const float lambda = param;
   if (n_samples < 0) return APS_ERR_SHAPE;
   if (u_tex && (tex_size < 1 || tex_size > kMaxTexSize)) return APS_ERR_ARG;
   if (levels < 1 || levels > APS_MAX_LEVELS) return APS_ERR_UNSUPPORTED;
   if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
-  if (mode != APS_HARD && mode != APS_RELAXED) return APS_ERR_ARG;
-  if (mode == APS_RELAXED && !(lambda >= 1.f)) return APS_ERR_ARG;
+  if (mode < APS_HARD || mode > APS_DASR) return APS_ERR_ARG;
+  if (mode == APS_RELAXED && !(param >= 1.f)) return APS_ERR_ARG;
+  if (mode == APS_GUMBEL && !(param > 0.f)) return APS_ERR_ARG;
   const int div = 1 << (levels - 1);
   if (H % div || W % div) return APS_ERR_SHAPE;
   if ((size_t)N * H * W > 0x7fffffffull) return APS_ERR_SHAPE;
@@ -703,11 +761,11 @@ int aps_scatter_samples_tex(const float* s, const uint8_t* count, const int32_t*
     if (!L[l]) return APS_ERR_NULL;
     lp.p[l] = reinterpret_cast<float4*>(L[l]);
   }
-  const float hfac = 2.f * lambda / (2.f * lambda - 1.f);
+  const float hfac = mode == APS_RELAXED ? 2.f * lambda / (2.f * lambda - 1.f) : 1.f;
   dim3 grid((W + 15) / 16, (H + 15) / 16, N);
   k_scatter<<<grid, 256, 0, as_stream(stream)>>>(s, count, pixel_offset,
                                                  reinterpret_cast<const float4*>(samples),
-                                                 n_samples, H, W, levels, mode == APS_RELAXED, lambda, hfac, seed,
+                                                 n_samples, H, W, levels, mode, param, hfac, seed,
                                                  frame, USource{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W},
                                                  lp);
   APS_LAUNCH_CHECK();
@@ -754,22 +812,26 @@ int aps_scatter_samples_bwd(const float* s, const uint8_t* count, const int32_t*
                             int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
                             const float* const* grad_L, float* grad_s, int accumulate,
                             void* stream) {
-  return aps_scatter_samples_bwd_tex(s, count, pixel_offset, samples, n_samples, N, H, W, levels,
-                                     mode, lambda, seed, frame, nullptr, 0, grad_L, grad_s,
-                                     accumulate, stream);
+  if (mode != APS_HARD && mode != APS_RELAXED) return APS_ERR_ARG;
+  return aps_scatter_samples_bwd_ex(s, count, pixel_offset, samples, n_samples, N, H, W, levels,
+                                    mode, lambda, seed, frame, nullptr, 0, nullptr, grad_L, grad_s,
+                                    accumulate, stream);
 }
 
-int aps_scatter_samples_bwd_tex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
-                                const float* samples, int64_t n_samples, int N, int H, int W,
-                                int levels, int mode, float lambda, uint64_t seed, uint32_t frame,
-                                const float* u_tex, int tex_size, const float* const* grad_L,
-                                float* grad_s, int accumulate, void* stream) {
+int aps_scatter_samples_bwd_ex(const float* s, const uint8_t* count, const int32_t* pixel_offset,
+                               const float* samples, int64_t n_samples, int N, int H, int W,
+                               int levels, int mode, float param, uint64_t seed, uint32_t frame,
+                               const float* u_tex, int tex_size, const float* L_ref,
+                               const float* const* grad_L, float* grad_s, int accumulate,
+                               void* stream) {
+  const float lambda = param;
   if (n_samples < 0) return APS_ERR_SHAPE;
   if (u_tex && (tex_size < 1 || tex_size > kMaxTexSize)) return APS_ERR_ARG;
   if (levels < 1 || levels > APS_MAX_LEVELS) return APS_ERR_UNSUPPORTED;
   if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
-  if (mode != APS_HARD && mode != APS_RELAXED) return APS_ERR_ARG;
-  if (mode == APS_RELAXED && !(lambda >= 1.f)) return APS_ERR_ARG;
+  if (mode < APS_HARD || mode > APS_DASR) return APS_ERR_ARG;
+  if (mode == APS_RELAXED && !(param >= 1.f)) return APS_ERR_ARG;
+  if (mode == APS_GUMBEL && !(param > 0.f)) return APS_ERR_ARG;
   const int div = 1 << (levels - 1);
   if (H % div || W % div) return APS_ERR_SHAPE;
   const size_t npix = (size_t)N * H * W;
@@ -777,16 +839,17 @@ int aps_scatter_samples_bwd_tex(const float* s, const uint8_t* count, const int3
   if (npix == 0) return APS_OK;
   if (!s || !count || !pixel_offset || !grad_L || !grad_s || (!samples && n_samples > 0))
     return APS_ERR_NULL;
+  if (mode == APS_DASR && !L_ref) return APS_ERR_NULL;
   GradLevels g{};
   for (int l = 0; l < levels; ++l) {
     if (!grad_L[l]) return APS_ERR_NULL;
     g.p[l] = reinterpret_cast<const float4*>(grad_L[l]);
   }
-  const float hfac = 2.f * lambda / (2.f * lambda - 1.f);
+  const float hfac = mode == APS_RELAXED ? 2.f * lambda / (2.f * lambda - 1.f) : 1.f;
   k_scatter_bwd<<<(unsigned)((npix + 255) / 256), 256, 0, as_stream(stream)>>>(
       s, count, pixel_offset, reinterpret_cast<const float4*>(samples), n_samples, N, H, W, levels,
-      mode == APS_RELAXED, lambda, hfac, seed, frame,
-      USource{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W}, g, grad_s, accumulate);
+      mode, param, hfac, seed, frame, USource{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W},
+      reinterpret_cast<const float4*>(L_ref), g, grad_s, accumulate);
   APS_LAUNCH_CHECK();
   return APS_OK;
 }

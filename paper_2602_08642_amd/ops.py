@@ -95,8 +95,17 @@ def _tex(u_tex):
     return _p(u_tex), u_tex.shape[0]
 
 
+_ROUNDING = {"stochastic": L.APS_ROUND_STOCHASTIC, "holdout": L.APS_ROUND_HOLDOUT,
+             "deterministic": L.APS_ROUND_DETERMINISTIC}
+_MODES = {"hard": L.APS_HARD, "relaxed": L.APS_RELAXED, "straight_through": L.APS_STRAIGHT_THROUGH,
+          "gumbel": L.APS_GUMBEL, "dasr": L.APS_DASR}
+# the mask rounding each scatter mode reads
+MODE_ROUNDING = {"hard": "stochastic", "relaxed": "stochastic", "straight_through": "holdout",
+                 "gumbel": "holdout", "dasr": "deterministic"}
+
+
 def sample_mask(s, seed: int, frame: int, capacity: int | None = None, want_p=False, status=None,
-                u_tex=None):
+                u_tex=None, rounding: str = "stochastic"):
     _need(s, "s", _F32)
     N, H, W = s.shape
     dev = s.device
@@ -112,9 +121,9 @@ def sample_mask(s, seed: int, frame: int, capacity: int | None = None, want_p=Fa
     nb = lib.aps_sample_mask_workspace_size(N, H, W)
     ws = WS.get(nb, dev)
     tp, T = _tex(u_tex)
-    L.check(lib.aps_sample_mask_tex(_p(s), N, H, W, seed, frame, tp, T, _p(count), _p(poff),
-                                    _p(spix), capacity, _p(total), _p(p), _p(ws), nb, _p(status),
-                                    _stream()),
+    L.check(lib.aps_sample_mask_ex(_p(s), N, H, W, seed, frame, tp, T, _ROUNDING[rounding], _p(count),
+                                   _p(poff), _p(spix), capacity, _p(total), _p(p), _p(ws), nb,
+                                   _p(status), _stream()),
             "sample_mask")
     return dict(count=count, pixel_offset=poff, sample_pixel=spix, total=total, p=p,
                 capacity=capacity)
@@ -133,17 +142,20 @@ def fixture_render(pool, count, pixel_offset, capacity: int):
 # ------------------------------------------------------------------ scatter (a4)
 
 def scatter_samples(s, count, pixel_offset, samples, levels: int, mode: str = "hard",
-                    lam: float = 10.0, seed: int = 0, frame: int = 0, u_tex=None):
+                    lam: float = 10.0, seed: int = 0, frame: int = 0, u_tex=None, tau: float = 0.5):
+    """mode: hard, relaxed (lam), straight_through, gumbel (tau) or dasr; the mask must have been
+    drawn with MODE_ROUNDING[mode]."""
     _need(s, "s", _F32)
     _need(samples, "samples", _F32)
     N, H, W = s.shape
     Ls = [torch.empty((N, H >> l, W >> l, 4), dtype=_F32, device=s.device) for l in range(levels)]
     arr = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in Ls])
-    m = L.APS_HARD if mode == "hard" else L.APS_RELAXED
+    m = _MODES[mode]
     tp, T = _tex(u_tex)
-    L.check(L.load().aps_scatter_samples_tex(_p(s), _p(count), _p(pixel_offset), _p(samples),
-                                             samples.shape[0], N, H, W, levels, m, lam, seed, frame,
-                                             tp, T, arr, _stream()),
+    L.check(L.load().aps_scatter_samples_ex(_p(s), _p(count), _p(pixel_offset), _p(samples),
+                                            samples.shape[0], N, H, W, levels, m,
+                                            tau if mode == "gumbel" else lam, seed, frame,
+                                            tp, T, arr, _stream()),
             "scatter_samples")
     return Ls
 
@@ -355,19 +367,21 @@ def denoise_pyramid_bwd(Ls, logits, KD: int, KU: int, KT: int, prev, mv, grad_ou
 
 
 def scatter_samples_bwd(s, count, pixel_offset, samples, grad_L, mode="relaxed", lam=10.0,
-                        seed=0, frame=0, grad_s=None, u_tex=None):
+                        seed=0, frame=0, grad_s=None, u_tex=None, tau: float = 0.5, L_ref=None):
     _need(s, "s", _F32)
     N, H, W = s.shape
     acc = grad_s is not None
     if grad_s is None:
         grad_s = torch.empty_like(s)
     arr = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in grad_L])
-    m = L.APS_HARD if mode == "hard" else L.APS_RELAXED
+    m = _MODES[mode]
     tp, T = _tex(u_tex)
-    L.check(L.load().aps_scatter_samples_bwd_tex(_p(s), _p(count), _p(pixel_offset), _p(samples),
-                                                 samples.shape[0], N, H, W, len(grad_L), m, lam,
-                                                 seed, frame, tp, T, arr, _p(grad_s), int(acc),
-                                                 _stream()),
+    if L_ref is not None:
+        _need(L_ref, "L_ref", _F32)
+    L.check(L.load().aps_scatter_samples_bwd_ex(_p(s), _p(count), _p(pixel_offset), _p(samples),
+                                                samples.shape[0], N, H, W, len(grad_L), m,
+                                                tau if mode == "gumbel" else lam, seed, frame, tp, T,
+                                                _p(L_ref), arr, _p(grad_s), int(acc), _stream()),
             "scatter_samples_bwd")
     return grad_s
 

@@ -71,10 +71,14 @@ def test_mask_texture_argument_checks(ops, tex64):
     ws = torch.empty(lib.aps_sample_mask_workspace_size(1, 8, 8), dtype=torch.uint8, device=DEV)
     t = torch.tensor(tex64, device=DEV)
     for bad in (0, 5000):
-        assert lib.aps_sample_mask_tex(ops._p(s), 1, 8, 8, 1, 0, ops._p(t), bad, ops._p(r["count"]),
-                                       ops._p(r["pixel_offset"]), ops._p(r["sample_pixel"]),
-                                       r["capacity"], ops._p(r["total"]), None, ops._p(ws), ws.numel(),
-                                       None, ops._stream()) == L.APS_ERR_ARG
+        assert lib.aps_sample_mask_ex(ops._p(s), 1, 8, 8, 1, 0, ops._p(t), bad, L.APS_ROUND_STOCHASTIC,
+                                      ops._p(r["count"]), ops._p(r["pixel_offset"]), ops._p(r["sample_pixel"]),
+                                      r["capacity"], ops._p(r["total"]), None, ops._p(ws), ws.numel(),
+                                      None, ops._stream()) == L.APS_ERR_ARG
+    assert lib.aps_sample_mask_ex(ops._p(s), 1, 8, 8, 1, 0, None, 0, 3, ops._p(r["count"]),
+                                  ops._p(r["pixel_offset"]), ops._p(r["sample_pixel"]), r["capacity"],
+                                  ops._p(r["total"]), None, ops._p(ws), ws.numel(), None,
+                                  ops._stream()) == L.APS_ERR_ARG
     with pytest.raises(ValueError):
         ops.sample_mask(s, 1, 0, u_tex=t[:, :32].contiguous())
 

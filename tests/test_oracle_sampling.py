@@ -290,3 +290,14 @@ def test_scatter_texture_relaxed_limit_is_hard():
     assert torch.allclose(rel, hard, rtol=1e-5, atol=1e-6)
     # and the Philox u would have given another mask
     assert not np.array_equal(sampling.mask(s, 21, 2)["count"], m["count"])
+
+
+def test_mask_rounding_variants():
+    s = np.array([[[0.0, 0.3, 0.5, 0.75, 1.0, 1.49999, 1.5, 2.2, 3.999]]], np.float32)
+    m_h = sampling.mask(s, 1, 0, rounding="holdout")["count"][0, 0].tolist()
+    m_d = sampling.mask(s, 1, 0, rounding="deterministic")["count"][0, 0].tolist()
+    assert m_h == [0, 1, 1, 1, 1, 2, 2, 3, 4]                 # floor(s) + [p > 0]
+    assert m_d == [0, 0, 1, 1, 1, 1, 2, 2, 4]                 # round half up: floor(s + 1/2)
+    st = sampling.mask(s, 1, 0)
+    fl = np.floor(s.astype(np.float64))
+    assert np.array_equal(st["count"], (fl + (st["u"] < s - fl)).astype(np.uint8))
