@@ -151,3 +151,36 @@ def test_first_frame_excludes_temporal():
     z2 = [z[0][..., :34], z[1]]
     b = filt.denoise_pyramid(L, z2, KD, KU, KT)[0]
     assert torch.equal(a, b)
+
+
+def test_demodulation_pins():
+    """d = 1 at z = 0 (identity); a constant z scales the filter input and output by inverse
+    factors, so a linear reconstruction is unchanged; levels are block means; |z| is clamped."""
+    from oracle import demod
+    g = torch.Generator().manual_seed(3)
+    N, H, W, levels, KD, KU, KT = 1, 16, 24, 3, 5, 3, 3
+    L = [torch.randn(N, H >> l, W >> l, 4, generator=g, dtype=torch.float64) for l in range(levels)]
+    for t in L:
+        t[..., 3] = 0
+    Ks = [KD * KD + (KU * KU if l < levels - 1 else 0) for l in range(levels)]
+    z = [torch.randn(N, H >> l, W >> l, Ks[l], generator=g, dtype=torch.float64) for l in range(levels)]
+    # identity at z = 0
+    zero = torch.zeros(N, H, W, 3, dtype=torch.float64)
+    Ld = demod.demodulate(L[0], zero, levels)
+    assert torch.equal(Ld[0], L[0])
+    # levels are the block means of level 0
+    pool = lambda x: torch.nn.functional.avg_pool2d(x.permute(0, 3, 1, 2), 2).permute(0, 2, 3, 1)
+    assert torch.allclose(Ld[1], pool(Ld[0]), rtol=1e-14, atol=1e-15)
+    assert torch.allclose(Ld[2], pool(pool(Ld[0])), rtol=1e-14, atol=1e-15)
+    # a constant map: out = d * F(L / d) = F(L) for the linear pyramid
+    c = torch.full((N, H, W, 3), 0.7, dtype=torch.float64)
+    pyr = demod.demodulate(L[0], c, levels)
+    ref = filt.denoise_pyramid(demod.demodulate(L[0], zero, levels), z, KD, KU, KT)[0]
+    out = demod.remodulate(filt.denoise_pyramid(pyr, z, KD, KU, KT)[0], c)
+    assert torch.allclose(out, ref, rtol=1e-12, atol=1e-12)
+    # per-pixel: the map divides exactly where it is predicted
+    zz = torch.clamp(torch.randn(N, H, W, 3, generator=g, dtype=torch.float64), -3, 3) * 2   # inside the clamp
+    Ld = demod.demodulate(L[0], zz, 1)[0]
+    assert torch.allclose(Ld[..., :3] * torch.exp(zz), L[0][..., :3], rtol=1e-13)
+    assert torch.equal(demod.demod_map(torch.tensor([-20.0, 20.0], dtype=torch.float64)),
+                       torch.exp(torch.tensor([-8.0, 8.0], dtype=torch.float64)))
