@@ -44,7 +44,7 @@ def filter_bytes(cfg):
     """Algorithmic HBM bytes of the gathering pyramid per frame (logits, L^l, output, coarse
     level, and at level 0 with the temporal term the previous output and motion vectors)."""
     lb = 4 if cfg.logit_dtype.itemsize == 4 else 2
-    ks = cfg.head_channels()
+    ks = cfg.filter_channels()
     tot = 0
     for l in range(cfg.levels):
         px = (cfg.H >> l) * (cfg.W >> l)
@@ -54,6 +54,10 @@ def filter_bytes(cfg):
         if l == 0 and cfg.temporal:
             b += 16 + 8
         tot += px * b
+    if cfg.demod:   # demodulation: L0 + d in, the demodulated pyramid out; remodulation: in, d, out
+        px = cfg.H * cfg.W
+        tot += px * (16 + 3 * lb) + sum(16 * ((cfg.H >> l) * (cfg.W >> l)) for l in range(cfg.levels))
+        tot += px * (16 + 3 * lb + 16)
     return tot
 
 
@@ -161,7 +165,7 @@ def bench_config(name, steps, warmup, dev, seed=2602):
         else:
             z = r.logits(aux, Ls[0], s)
         mark(5)
-        out = ops.denoise_pyramid(Ls, z, cfg.KD, cfg.KU, cfg.KT, prev, mv)
+        out = r.filter(Ls, z, prev, mv)
         mark(6)
         return out
 
@@ -211,7 +215,8 @@ def bench_config(name, steps, warmup, dev, seed=2602):
                   + (f" / kt {cfg.KT}x{cfg.KT}" if cfg.temporal else "")
                   + f", U-Net 32-64-128-256 with {cfg.levels} heads ({'fp32' if fp32 else 'bf16'} MFMA)"
                   + (", sampler at quarter resolution" if cfg.density_scale == 2 else "")
-                  + (", blue-noise u" if cfg.u_noise == "blue" else "")))
+                  + (", blue-noise u" if cfg.u_noise == "blue" else "")
+                  + (", learned demodulation" if cfg.demod else "")))
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2602_08642_amd", "weights", "c4_trained.npz")

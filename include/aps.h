@@ -269,6 +269,18 @@ int aps_upsample(const float* coarse, const void* logits, int logit_dtype, int k
                  int KU, int KT, int has_temporal, int N, int H, int W, float* accum_out,
                  void* stream);
 
+/* ---------------------------------------------------------------- learned demodulation
+ * Sec. 6.2 (learned demodulation): the denoiser predicts d = exp(clamp(z, -8, 8)) per pixel
+ * and channel, z being three channels of the level-0 logits tensor z [N,H,W,z_stride] (z_dtype
+ * APS_F32 or APS_BF16) from channel z_offset (z_stride >= z_offset + 3).  aps_demodulate: Ld[0]
+ * = L0 / d (RGB; A written 0) and Ld[l] its 2^l x 2^l block means (App. A eq. app-pyramid),
+ * Ld[l] float32 RGBA [N, H>>l, W>>l], H and W divisible by 2^(levels-1); the filter then runs on
+ * Ld.  aps_remodulate: out = d * in (RGB), in and out float32 RGBA [N,H,W]; out may alias in. */
+int aps_demodulate(const float* L0, const void* z, int z_dtype, int z_stride, int z_offset, int N,
+                   int H, int W, int levels, float* const* Ld, void* stream);
+int aps_remodulate(const float* in, const void* z, int z_dtype, int z_stride, int z_offset, int N,
+                   int H, int W, float* out, void* stream);
+
 /* ---------------------------------------------------------------- a10: backward passes
  * All gradients are float32 unless a dtype argument says otherwise.  "Written" outputs are
  * overwritten; "accumulated" ones are added to (the caller zeroes them first). */
@@ -313,6 +325,18 @@ int aps_scatter_samples_bwd_ex(const float* s, const uint8_t* count, const int32
                                const float* u_tex, int tex_size, const float* L_ref,
                                const float* const* grad_L, float* grad_s, int accumulate,
                                void* stream);
+
+/* Backward of aps_demodulate / aps_remodulate.  grad_Ld[l] float32 RGBA per level (the
+ * filter's gradient w.r.t. its input pyramid); grad_L0 float32 RGBA [N,H,W]; grad_z float32
+ * [N,H,W,3] (dLoss/dz of the three demodulation channels, 0 where the clamp is active); with
+ * accumulate != 0 both outputs are added to, else written.  aps_remodulate_bwd: grad_out of
+ * out = d * in gives grad_in = grad_out * d and grad_z = grad_out * out. */
+int aps_demodulate_bwd(const float* L0, const void* z, int z_dtype, int z_stride, int z_offset,
+                       int N, int H, int W, int levels, const float* const* grad_Ld,
+                       float* grad_L0, float* grad_z, int accumulate, void* stream);
+int aps_remodulate_bwd(const float* in, const void* z, int z_dtype, int z_stride, int z_offset,
+                       int N, int H, int W, const float* grad_out, float* grad_in, float* grad_z,
+                       int accumulate, void* stream);
 
 /* Budget normalisation backward (Sec. 3): grad_z (written) = c1 sm (g - sum(sm g)) per frame,
  * c1 = (1-f) B Npx; fixed-tree reductions (deterministic). */

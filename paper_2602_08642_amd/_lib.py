@@ -42,6 +42,10 @@ SIGNATURES = {
     "aps_density_predict_workspace_size": (SZ, [I, I, I, I, I]),
     "aps_density_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, F, F, P, P, P, SZ, P, P]),
     "aps_avgpool2": (I, [P, I, I, I, I, I, P, P]),
+    "aps_demodulate": (I, [P, P, I, I, I, I, I, I, I, P, P]),
+    "aps_remodulate": (I, [P, P, I, I, I, I, I, I, P, P]),
+    "aps_demodulate_bwd": (I, [P, P, I, I, I, I, I, I, I, P, P, P, I, P]),
+    "aps_remodulate_bwd": (I, [P, P, I, I, I, I, I, I, P, P, P, I, P]),
     "aps_upsample_nearest2": (I, [P, I, I, I, P, P]),
     "aps_sample_mask_workspace_size": (SZ, [I, I, I]),
     "aps_sample_mask": (I, [P, I, I, I, U64, U32, P, P, P, I64, P, P, P, SZ, P, P]),

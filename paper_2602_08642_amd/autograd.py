@@ -146,6 +146,47 @@ def denoise(Ls, logits, KD, KU, KT, prev=None, mv=None):
     return Denoise.apply(KD, KU, KT, mv, prev, len(Ls), *Ls, *logits)
 
 
+def _z_grad(z0, k0, gz):
+    """dLoss/dz of the three demodulation channels as a gradient of the whole level-0 logits."""
+    g = torch.zeros_like(z0)
+    g[..., k0:k0 + 3] = gz.to(z0.dtype)
+    return g
+
+
+class Demod(torch.autograd.Function):
+    """Learned demodulation (Sec. 6.2): the pyramid of L0 / d, d from the level-0 logits."""
+
+    @staticmethod
+    def forward(ctx, L0, z0, k0: int, levels: int):
+        ctx.k = (k0, levels)
+        ctx.save_for_backward(L0, z0)
+        return tuple(ops.demodulate(L0, z0, k0, levels))
+
+    @staticmethod
+    def backward(ctx, *gLd):
+        k0, levels = ctx.k
+        L0, z0 = ctx.saved_tensors
+        g = [t.contiguous() if t is not None else torch.zeros((L0.shape[0], L0.shape[1] >> l, L0.shape[2] >> l, 4),
+                                                             dtype=torch.float32, device=L0.device)
+             for l, t in enumerate(gLd)]
+        gL0, gz = ops.demodulate_bwd(L0, z0, k0, g)
+        return gL0, _z_grad(z0, k0, gz), None, None
+
+
+class Remod(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, z0, k0: int):
+        ctx.k0 = k0
+        ctx.save_for_backward(x, z0)
+        return ops.remodulate(x, z0, k0)
+
+    @staticmethod
+    def backward(ctx, gout):
+        x, z0 = ctx.saved_tensors
+        gx, gz = ops.remodulate_bwd(x, z0, ctx.k0, gout.contiguous())
+        return gx, _z_grad(z0, ctx.k0, gz), None
+
+
 class TMOLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, out, prev_out, ref, prev_ref, mv, params):

@@ -276,6 +276,58 @@ def upsample_nearest2(s_q):
     return s
 
 
+def demodulate(L0, z0, z_offset: int, levels: int):
+    """Learned demodulation: pyramid of L0 / exp(z), z = z0[..., z_offset:z_offset+3]."""
+    _need(L0, "L0", _F32)
+    _need(z0, "z0")
+    N, H, W, _ = L0.shape
+    Ld = [torch.empty((N, H >> l, W >> l, 4), dtype=_F32, device=L0.device) for l in range(levels)]
+    arr = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in Ld])
+    L.check(L.load().aps_demodulate(_p(L0), _p(z0), _dt(z0.dtype), z0.shape[-1], z_offset, N, H, W,
+                                    levels, arr, _stream()), "demodulate")
+    return Ld
+
+
+def remodulate(x, z0, z_offset: int, out=None):
+    _need(x, "x", _F32)
+    _need(z0, "z0")
+    N, H, W, _ = x.shape
+    out = torch.empty_like(x) if out is None else out
+    L.check(L.load().aps_remodulate(_p(x), _p(z0), _dt(z0.dtype), z0.shape[-1], z_offset, N, H, W,
+                                    _p(out), _stream()), "remodulate")
+    return out
+
+
+def demodulate_bwd(L0, z0, z_offset: int, grad_Ld, grad_L0=None, grad_z=None):
+    """-> (grad_L0 [N,H,W,4], grad_z [N,H,W,3]); given buffers are accumulated into."""
+    _need(L0, "L0", _F32)
+    N, H, W, _ = L0.shape
+    acc = grad_L0 is not None
+    if acc != (grad_z is not None):
+        raise ValueError("pass both gradient buffers to accumulate, or neither")
+    grad_L0 = torch.empty_like(L0) if grad_L0 is None else grad_L0
+    grad_z = torch.empty((N, H, W, 3), dtype=_F32, device=L0.device) if grad_z is None else grad_z
+    arr = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in grad_Ld])
+    L.check(L.load().aps_demodulate_bwd(_p(L0), _p(z0), _dt(z0.dtype), z0.shape[-1], z_offset, N, H, W,
+                                        len(grad_Ld), arr, _p(grad_L0), _p(grad_z), int(acc), _stream()),
+            "demodulate_bwd")
+    return grad_L0, grad_z
+
+
+def remodulate_bwd(x, z0, z_offset: int, grad_out, grad_in=None, grad_z=None):
+    _need(x, "x", _F32)
+    N, H, W, _ = x.shape
+    acc = grad_in is not None
+    if acc != (grad_z is not None):
+        raise ValueError("pass both gradient buffers to accumulate, or neither")
+    grad_in = torch.empty_like(x) if grad_in is None else grad_in
+    grad_z = torch.empty((N, H, W, 3), dtype=_F32, device=x.device) if grad_z is None else grad_z
+    L.check(L.load().aps_remodulate_bwd(_p(x), _p(z0), _dt(z0.dtype), z0.shape[-1], z_offset, N, H, W,
+                                        _p(grad_out), _p(grad_in), _p(grad_z), int(acc), _stream()),
+            "remodulate_bwd")
+    return grad_in, grad_z
+
+
 def round_kstride(K: int, dtype) -> int:
     v = 8 if dtype == _BF16 else 4
     return (K + v - 1) // v * v

@@ -33,6 +33,7 @@ class FrameConfig:
     kernel_net: str = "unet"          # "unet" or "cnn3" (single-level 3-layer CNN)
     density_scale: int = 1            # 2: sampler at a quarter of the pixels (Sec. 7)
     u_noise: str = "philox"           # u of the mask: "philox" or "blue" (void-and-cluster texture)
+    demod: bool = False               # learned demodulation (Sec. 6.2): 3 more level-0 head channels
 
     @property
     def sampler_cin(self) -> int:
@@ -42,13 +43,22 @@ class FrameConfig:
     def kernel_cin(self) -> int:
         return 16
 
-    def head_channels(self):
+    def filter_channels(self):
+        """Kernel logits per level (the joint softmax of App. A)."""
         out = []
         for l in range(self.levels):
             k = self.KD * self.KD + (self.KU * self.KU if l < self.levels - 1 else 0)
             if l == 0 and self.temporal:
                 k += self.KT * self.KT
             out.append(k)
+        return out
+
+    def head_channels(self):
+        """U-Net head outputs per level: the kernel logits, and at level 0 the three channels of
+        the demodulation map after them when demod is on."""
+        out = self.filter_channels()
+        if self.demod:
+            out[0] += 3
         return out
 
 
@@ -67,7 +77,7 @@ CONFIGS = {
     # kt 5x5 (54-way softmax at level 0), with the quarter-resolution density map of Sec. 7;
     # 1080 rows are not divisible by 2^4, so the frame is 1080p padded to 1088 rows
     "paper": FrameConfig("paper", 1088, 1920, 0.25, 5, 5, 2, 5, True, BF16, BF16, density_scale=2,
-                         u_noise="blue"),
+                         u_noise="blue", demod=True),
 }
 
 
@@ -102,6 +112,7 @@ class FrameRenderer:
         if kernel_weights is not None:
             self.knet = ops.Net(kernel_spec(cfg), kernel_weights, cfg.net_dtype, self.device)
         self._const_logits = None
+        self.history = None
         self.u_tex = None
         if cfg.u_noise == "blue":   # a 64x64 void-and-cluster threshold texture (Sec. 6.3)
             import procgen
@@ -153,20 +164,38 @@ class FrameRenderer:
         return ops.kernel_predict(self.knet, feat, cfg.head_channels(), cfg.logit_dtype)
 
     def reconstruct(self, aux, s, req, samples, seed: int, frame: int, prev=None, mv=None,
-                    mode="hard", lam=10.0):
+                    mode="hard", lam=10.0, history=None):
         cfg = self.cfg
         Ls = ops.scatter_samples(s, req["count"], req["pixel_offset"], samples, cfg.levels, mode,
                                  lam, seed, frame, u_tex=self.u_tex)
         use_prev = prev if cfg.temporal else None
         use_mv = mv if cfg.temporal else None
         z = self.logits(aux, Ls[0], s, use_prev, use_mv)
-        out = ops.denoise_pyramid(Ls, z, cfg.KD, cfg.KU, cfg.KT, use_prev, use_mv)
+        hist = (history if history is not None else prev) if cfg.temporal else None
+        out, self.history = self.filter(Ls, z, hist, use_mv, want_history=True)
         return out, Ls, z
 
-    def step(self, aux, render, seed: int, frame: int, prev=None, mv=None):
-        """One frame; render(req) -> samples [capacity, 4] stands in for the path tracer."""
+    def filter(self, Ls, z, history=None, mv=None, want_history=False):
+        """Gathering pyramid.  With learned demodulation the pyramid of L0 / d is filtered and the
+        result multiplied by d (d from the level-0 head channels after the kernel logits); the
+        filter then works in demodulated space throughout, so its temporal input (history) is the
+        previous frame's demodulated reconstruction, which want_history also returns."""
+        cfg = self.cfg
+        if cfg.demod:
+            k0 = cfg.filter_channels()[0]
+            Ld = ops.demodulate(Ls[0], z[0], k0, cfg.levels)
+            out_d = ops.denoise_pyramid(Ld, z, cfg.KD, cfg.KU, cfg.KT, history, mv)
+            out = ops.remodulate(out_d, z[0], k0)
+            return (out, out_d) if want_history else out
+        out = ops.denoise_pyramid(Ls, z, cfg.KD, cfg.KU, cfg.KT, history, mv)
+        return (out, out) if want_history else out
+
+    def step(self, aux, render, seed: int, frame: int, prev=None, mv=None, history=None):
+        """One frame; render(req) -> samples [capacity, 4] stands in for the path tracer.  prev is
+        the previous output (network inputs); history the filter's temporal input (the previous
+        "history" entry; prev when not given)."""
         s = self.density(aux, prev if self.cfg.temporal else None, mv if self.cfg.temporal else None)
         req = self.request(s, seed, frame)
         samples = render(req)
-        out, Ls, z = self.reconstruct(aux, s, req, samples, seed, frame, prev, mv)
-        return dict(out=out, s=s, req=req, L=Ls, logits=z)
+        out, Ls, z = self.reconstruct(aux, s, req, samples, seed, frame, prev, mv, history=history)
+        return dict(out=out, history=self.history, s=s, req=req, L=Ls, logits=z)

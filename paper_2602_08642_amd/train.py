@@ -148,7 +148,10 @@ class _Gate(torch.autograd.Function):
 
 
 def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relaxed",
-                  uniform=False, lam=10.0):
+                  uniform=False, lam=10.0, history=None, want_history=False):
+    """One frame with autograd.  prev: the previous output (network inputs); history: the filter's
+    temporal input (prev when None; with learned demodulation the previous demodulated
+    reconstruction, which want_history returns as a third value)."""
     N = aux.shape[0]
     if uniform or dnet is None:
         s = torch.full((N, cfg.H, cfg.W), cfg.budget, dtype=F32, device=aux.device)
@@ -165,8 +168,15 @@ def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relax
     else:
         feat = ag.Features.apply("kernel", aux, Ls[0], s, prev, mv, cfg.kernel_cin, cfg.net_dtype)
         logits = unet_forward(knet, cfg, feat)
-    out = ag.denoise(list(Ls), logits, cfg.KD, cfg.KU, cfg.KT, prev, mv)
-    return out, s
+    hist = prev if history is None else history
+    if cfg.demod:
+        k0 = cfg.filter_channels()[0]
+        Ld = ag.Demod.apply(Ls[0], logits[0], k0, cfg.levels)
+        out_h = ag.denoise(list(Ld), logits, cfg.KD, cfg.KU, cfg.KT, hist, mv)
+        out = ag.Remod.apply(out_h, logits[0], k0)
+    else:
+        out = out_h = ag.denoise(list(Ls), logits, cfg.KD, cfg.KU, cfg.KT, hist, mv)
+    return (out, s, out_h) if want_history else (out, s)
 
 
 # ------------------------------------------------------------------ training
@@ -208,7 +218,7 @@ def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, 
         if ci not in data:
             data[ci] = make_clips(pool_clips[ci], cfg.H, cfg.W, tc.frames, device, rng_seed=ci)
         cb = data[ci]
-        prev, prev_ref, gate = None, None, None
+        prev, prev_h, prev_ref, gate = None, None, None, None
         losses = []
         lo, hi = tc.budget_range
         bstep = float(math.exp(np.random.default_rng([tc.seed, step]).uniform(math.log(lo), math.log(hi))))
@@ -216,17 +226,18 @@ def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, 
         for t in range(tc.frames):
             pool = sample_pool(cb.ref[t], gen)
             pin = None if prev is None else _Gate.apply(prev, gate)
+            hin = None if prev_h is None else (pin if prev_h is prev else _Gate.apply(prev_h, gate))
             mv = cb.mv[t] if prev is not None else None
             seed = 1_000_003 * step + t
-            out, s = frame_forward(dnet, knet, cfg_s, cb.aux[t], pin, mv, pool, seed, t, "relaxed",
-                                   uniform=tc.uniform)
+            out, s, out_h = frame_forward(dnet, knet, cfg_s, cb.aux[t], pin, mv, pool, seed, t, "relaxed",
+                                          uniform=tc.uniform, history=hin, want_history=True)
             loss = ag.TMOLoss.apply(out, pin, cb.ref[t], prev_ref, mv, cb.params)
             loss.backward(retain_graph=True)
             if gate is not None:
                 gate["open"] = False        # frame t-2 stays out of later windows
             losses.append(loss.detach())
-            prev, prev_ref, gate = out, cb.ref[t], {"open": True}
-        del prev, out, loss, pin
+            prev, prev_h, prev_ref, gate = out, out_h, cb.ref[t], {"open": True}
+        del prev, prev_h, out, out_h, loss, pin
         # AdamW on the fp32 masters (gradients averaged over the frames)
         lr = cosine_lr(step - 1, tc.steps, tc.lr)
         gn = 0.0
@@ -283,13 +294,14 @@ def evaluate(cfg: FrameConfig, dnet, knet, seeds, frames=8, device="cuda", unifo
         cfg = dataclasses.replace(cfg, budget=budget)
     cb = make_clips(seeds, cfg.H, cfg.W, frames, device, randomise_tmo=False)
     gen = torch.Generator(device=device).manual_seed(gen_seed)
-    prev = None
+    prev = hist = None
     ps, rm = [], []
     for t in range(frames):
         pool = sample_pool(cb.ref[t], gen)
         mv = cb.mv[t] if prev is not None else None
-        out, _ = frame_forward(None if uniform else dnet, knet, cfg, cb.aux[t], prev, mv, pool,
-                               7_000_001 + t, t, "hard", uniform=uniform)
+        out, _, hist = frame_forward(None if uniform else dnet, knet, cfg, cb.aux[t], prev, mv, pool,
+                                     7_000_001 + t, t, "hard", uniform=uniform, history=hist,
+                                     want_history=True)
         prev = out
         ps.append(psnr_tonemapped(out, cb.ref[t], cb.params))
         r = cb.ref[t][..., :3]

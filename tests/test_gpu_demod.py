@@ -1,0 +1,121 @@
+"""Learned demodulation (Sec. 6.2): the demodulated pyramid, the remodulation and their gradients
+against the FP64 oracle, with the map read from the level-0 logits tensor."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import demod as odemod
+from tests._tol import assert_mag_close
+from tests.test_gpu_backward import assert_grad_close
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+F64 = torch.float64
+
+
+@pytest.fixture(scope="module")
+def ops():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2602_08642_amd import ops as o
+    return o
+
+
+def _inputs(N, H, W, ks, k0, dtype, seed):
+    g = torch.Generator().manual_seed(seed)
+    L0 = torch.randn(N, H, W, 4, generator=g) * 2
+    L0[..., 3] = 0
+    z0 = torch.randn(N, H, W, ks, generator=g)
+    z0[..., k0:k0 + 3] *= 3.0
+    z0[0, 0, 0, k0] = 9.5                  # clamped
+    z0[0, 0, 1, k0 + 1] = -12.0
+    return L0, z0.to(dtype)
+
+
+@pytest.mark.parametrize("case", [(1, 32, 48, 3, 64, 54, torch.bfloat16), (2, 24, 40, 4, 40, 34, torch.float32),
+                                  (1, 16, 16, 5, 64, 57, torch.bfloat16), (1, 20, 12, 1, 8, 3, torch.float32)])
+def test_demodulate_and_remodulate_match_oracle(ops, case):
+    N, H, W, levels, ks, k0, dt = case
+    L0, z0 = _inputs(N, H, W, ks, k0, dt, sum(case[:5]))
+    Ld = ops.demodulate(L0.to(DEV), z0.to(DEV), k0, levels)
+    zd = z0[..., k0:k0 + 3].double()
+    ref = odemod.demodulate(L0.double(), zd, levels)
+    mag = odemod.demodulate(L0.double().abs(), zd, levels)
+    for l in range(levels):
+        assert_mag_close(Ld[l], ref[l], mag[l], 1e-5, what=f"level {l}")
+        assert torch.all(Ld[l][..., 3] == 0)
+    x = torch.randn(N, H, W, 4, generator=torch.Generator().manual_seed(5))
+    out = ops.remodulate(x.to(DEV), z0.to(DEV), k0)
+    r = odemod.remodulate(x.double(), zd)
+    assert_mag_close(out, r, r.abs(), 1e-5, what="remodulate")
+    xd = x.to(DEV)
+    ops.remodulate(xd, z0.to(DEV), k0, out=xd)          # in place
+    assert torch.equal(xd, out)
+
+
+def test_demod_gradients_match_oracle(ops):
+    N, H, W, levels, ks, k0 = 2, 16, 24, 3, 40, 34
+    L0, z0 = _inputs(N, H, W, ks, k0, torch.float32, 9)
+    g = torch.Generator().manual_seed(10)
+    gLd = [torch.randn(N, H >> l, W >> l, 4, generator=g) for l in range(levels)]
+    gout = torch.randn(N, H, W, 4, generator=g)
+    x = torch.randn(N, H, W, 4, generator=g)
+    gL0, gz = ops.demodulate_bwd(L0.to(DEV), z0.to(DEV), k0, [t.to(DEV) for t in gLd])
+    gx, gz2 = ops.remodulate_bwd(x.to(DEV), z0.to(DEV), k0, gout.to(DEV))
+    L64 = L0.double().requires_grad_(True)
+    z64 = z0[..., k0:k0 + 3].double().requires_grad_(True)
+    pyr = odemod.demodulate(L64, z64, levels)
+    sum((p * t.double()).sum() for p, t in zip(pyr, gLd)).backward()
+    assert_grad_close(gL0[..., :3], L64.grad[..., :3], 1e-5, "dL0")
+    assert_grad_close(gz, z64.grad, 1e-5, "dz (demodulate)")
+    x64 = x.double().requires_grad_(True)
+    z64b = z0[..., k0:k0 + 3].double().requires_grad_(True)
+    (odemod.remodulate(x64, z64b) * gout.double()).sum().backward()
+    assert_grad_close(gx[..., :3], x64.grad[..., :3], 1e-5, "dx (remodulate)")
+    assert_grad_close(gz2, z64b.grad, 1e-5, "dz (remodulate)")
+    # accumulate: the second call adds
+    gL0b, gzb = ops.demodulate_bwd(L0.to(DEV), z0.to(DEV), k0, [t.to(DEV) for t in gLd],
+                                   grad_L0=gL0.clone(), grad_z=gz.clone())
+    assert torch.allclose(gL0b, 2 * gL0) and torch.allclose(gzb, 2 * gz)
+
+
+def test_zero_map_leaves_the_frame_unchanged(ops):
+    """d = 1 where the demodulation channels are 0: the demodulated path gives the plain
+    reconstruction bit for bit."""
+    from paper_2602_08642_amd import pipeline
+    cfg = dataclasses.replace(pipeline.CONFIGS["paper"], H=64, W=96)
+    plain = dataclasses.replace(cfg, demod=False)
+    r_d = pipeline.FrameRenderer(cfg, None, None, DEV, uniform=True)
+    r_p = pipeline.FrameRenderer(plain, None, None, DEV, uniform=True)
+    g = torch.Generator().manual_seed(12)
+    L0 = torch.randn(1, 64, 96, 4, generator=g)
+    L0[..., 3] = 0
+    Ls = [L0]
+    for l in range(1, cfg.levels):     # block means in the kernels' summation order
+        q = Ls[-1]
+        Ls.append(((q[:, 0::2, 0::2] + q[:, 0::2, 1::2]) + (q[:, 1::2, 0::2] + q[:, 1::2, 1::2])) * 0.25)
+    Ls = [t.to(DEV) for t in Ls]
+    ks = cfg.head_channels()
+    z = []
+    for l in range(cfg.levels):
+        t = torch.randn(1, 64 >> l, 96 >> l, ops.round_kstride(ks[l], torch.bfloat16), generator=g)
+        if l == 0:
+            t[..., cfg.filter_channels()[0]:] = 0
+        z.append(t.to(torch.bfloat16).to(DEV))
+    prev = torch.randn(1, 64, 96, 4, generator=g)
+    prev[..., 3] = 0
+    mv = torch.rand(1, 64, 96, 2, generator=g) * 6 - 3
+    a = r_d.filter(Ls, z, prev.to(DEV), mv.to(DEV))
+    b = r_p.filter(Ls, z, prev.to(DEV), mv.to(DEV))
+    assert torch.equal(a, b)
+
+
+def test_demod_channel_bounds(ops):
+    from paper_2602_08642_amd import _lib as L
+    L0 = torch.zeros(1, 8, 8, 4, device=DEV)
+    z0 = torch.zeros(1, 8, 8, 56, device=DEV)
+    with pytest.raises(L.ApsError):
+        ops.demodulate(L0, z0, 54, 1)               # channels 54..56 run past the stride
+    ops.demodulate(L0, z0, 53, 1)
+    torch.cuda.synchronize()

@@ -160,10 +160,12 @@ def test_scatter_five_levels(ops, mode):
 def test_paper_mode_frame(ops):
     """One temporal frame of the paper configuration (reduced to 64x96), random-init networks:
     quarter-resolution density, blue-noise mask, render stand-in, scatter into 5 levels,
-    five-head U-Net, 5-level 5/2/5 pyramid with the warped previous output."""
+    five-head U-Net, learned demodulation around the 5-level 5/2/5 pyramid with the warped
+    previous output."""
     from paper_2602_08642_amd import pipeline
     cfg = dataclasses.replace(pipeline.CONFIGS["paper"], H=64, W=96)
-    assert cfg.head_channels() == [54, 29, 29, 29, 25]
+    assert cfg.filter_channels() == [54, 29, 29, 29, 25]
+    assert cfg.head_channels() == [57, 29, 29, 29, 25]          # + the demodulation map (Sec. 6.2)
     dspec, kspec = pipeline.density_spec(cfg), pipeline.kernel_spec(cfg)
     dw, kw = procgen.init_weights(dspec, 51), procgen.init_weights(kspec, 52)
     r = pipeline.FrameRenderer(cfg, dw, kw, device=DEV)
@@ -206,9 +208,12 @@ def test_paper_mode_frame(ops):
     for l, K in enumerate(cfg.head_channels()):
         assert logits[l].shape[1:3] == (cfg.H >> l, cfg.W >> l)
         assert rel_norm(logits[l][..., :K].float().cpu(), zref[l]) < 2e-2, l
-    # the 5-level pyramid on the GPU's logits
-    L64 = [t.double().cpu() for t in Ls]
+    # learned demodulation around the 5-level pyramid, on the GPU's logits
+    from oracle import demod as odemod
     z64 = [t.double().cpu() for t in logits]
-    ref = ofilt.denoise_pyramid(L64, z64, 5, 2, 5, prev.double().cpu(), mv.double().cpu())[0]
-    mag = ofilt.denoise_magnitude(L64, z64, 5, 2, 5, prev.double().cpu(), mv.double().cpu())[0]
-    assert_mag_close(out[..., :3], ref[..., :3], mag[..., :3], 1e-5, what="paper frame")
+    zd = z64[0][..., 54:57]
+    Ld = odemod.demodulate(Ls[0].double().cpu(), zd, 5)
+    Lda = odemod.demodulate(Ls[0].double().cpu().abs(), zd, 5)
+    ref = odemod.remodulate(ofilt.denoise_pyramid(Ld, z64, 5, 2, 5, prev.double().cpu(), mv.double().cpu())[0], zd)
+    mag = odemod.remodulate(ofilt.denoise_magnitude(Lda, z64, 5, 2, 5, prev.double().cpu(), mv.double().cpu())[0], zd)
+    assert_mag_close(out[..., :3], ref[..., :3], mag[..., :3], 2e-5, what="paper frame")

@@ -24,10 +24,11 @@ def _small_cfg():
                                logit_dtype=torch.float32, widths=(8, 16, 16, 16))
 
 
-def test_frame_gradients_match_oracle():
+@pytest.mark.parametrize("demod", [False, True])
+def test_frame_gradients_match_oracle(demod):
     from paper_2602_08642_amd import autograd as ag
     from paper_2602_08642_amd import ops, pipeline, train
-    cfg = _small_cfg()
+    cfg = dataclasses.replace(_small_cfg(), demod=demod)
     N, H, W = 2, cfg.H, cfg.W
     dspec, kspec = pipeline.density_spec(cfg), pipeline.kernel_spec(cfg)
     dw = procgen.init_weights(dspec, 3)
@@ -62,7 +63,14 @@ def test_frame_gradients_match_oracle():
     Ls = osamp.pyramid(L0, cfg.levels)
     fk = ofeat.kernel_features(aux, L0, s64, p64, m64, cfg.kernel_cin)
     logits = ounet.unet_forward(fk, kwt, cfg.levels)
-    o64 = ofilt.denoise_pyramid(Ls, logits, cfg.KD, cfg.KU, cfg.KT, p64, m64)[0]
+    if demod:   # learned demodulation: the filter sees L0 / d, its output is multiplied by d
+        from oracle import demod as odemod
+        k0 = cfg.filter_channels()[0]
+        zd = logits[0][..., k0:k0 + 3]
+        o64 = odemod.remodulate(ofilt.denoise_pyramid(odemod.demodulate(L0, zd, cfg.levels), logits,
+                                                      cfg.KD, cfg.KU, cfg.KT, p64, m64)[0], zd)
+    else:
+        o64 = ofilt.denoise_pyramid(Ls, logits, cfg.KD, cfg.KU, cfg.KT, p64, m64)[0]
     ltot = 0
     for n in range(N):
         prm = dict(zip(["k", "alpha", "beta", "s", "h"], cb.params[n].double().cpu().tolist()))
