@@ -158,7 +158,8 @@ def bench_config(name, steps, warmup, dev, seed=2602):
                                  10.0, seed, frame, u_tex=r.u_tex)
         mark(3)
         if r.knet is not None:
-            feat = ops.assemble_features("kernel", aux, Ls[0], s, prev, mv, cfg.kernel_cin, cfg.net_dtype)
+            feat = ops.assemble_features("kernel", aux, Ls[0], s, prev, mv, cfg.kernel_cin, cfg.net_dtype,
+                                         lat=r._lat(prev))
         mark(4)
         if r.knet is not None:
             z = ops.kernel_predict(r.knet, feat, cfg.head_channels(), cfg.logit_dtype)
@@ -216,7 +217,8 @@ def bench_config(name, steps, warmup, dev, seed=2602):
                   + f", U-Net 32-64-128-256 with {cfg.levels} heads ({'fp32' if fp32 else 'bf16'} MFMA)"
                   + (", sampler at quarter resolution" if cfg.density_scale == 2 else "")
                   + (", blue-noise u" if cfg.u_noise == "blue" else "")
-                  + (", learned demodulation" if cfg.demod else "")))
+                  + (", learned demodulation" if cfg.demod else "")
+                  + (", recurrent latents" if cfg.latents else "")))
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2602_08642_amd", "weights", "c4_trained.npz")

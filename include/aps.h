@@ -217,13 +217,21 @@ int aps_scatter_samples_ex(const float* s, const uint8_t* count, const int32_t* 
 /* Network inputs (C <= 16 channels, zero padded), out [N,H,W,C] in out_dtype.
  *   APS_FEAT_SAMPLER: aux[0..6], then with prev: tonemap(W prev) RGB, valid
  *   APS_FEAT_KERNEL : aux[0..6], slog1p(L0) RGB, s, then with prev: slog1p(W prev) RGB, valid
- * aux float32 [N,H,W,8] (albedo 3, normal 3, log-depth 1, pad); C is 8 or 16; W prev = bilinear warp of the
+ * aux float32 [N,H,W,8] (albedo 3, normal 3, log-depth 1, pad); C is 8 or 16 (24 with
+ * latents, below); W prev = bilinear warp of the
  * previous output along mv (see aps_reproject); valid = the back-projected position lies in
  * the frame; slog1p(v) = sign(v) log(1+|v|); tonemap = the evaluation filmic curve of Sec. 5
  * (s = h = 0.5, contrast 0.4, exposure 0, saturation 1) followed by the sRGB transfer. */
 int aps_assemble_features(int kind, const float* aux, const float* L0, const float* s,
                           const float* prev, const float* mv, int N, int H, int W, int C,
                           int out_dtype, void* out, void* stream);
+/* The same with the recurrent latents (Sec. 3: the sampler and the denoiser share a latent
+ * feature space fed forward from the previous frame): lat float32 [N,H,W,4] (the previous
+ * frame's latents, see aps_remodulate) warped along mv like prev and appended as 4 channels
+ * after the temporal ones (requires prev); C is 8, 16 or 24. */
+int aps_assemble_features_ex(int kind, const float* aux, const float* L0, const float* s,
+                             const float* prev, const float* mv, const float* lat, int N, int H,
+                             int W, int C, int out_dtype, void* out, void* stream);
 
 /* ---------------------------------------------------------------- a5: kernel prediction
  * U-Net (2 x (3x3 conv + ReLU) per level, 2x2 average pool down, nearest-2x up + concat
@@ -275,11 +283,15 @@ int aps_upsample(const float* coarse, const void* logits, int logit_dtype, int k
  * APS_F32 or APS_BF16) from channel z_offset (z_stride >= z_offset + 3).  aps_demodulate: Ld[0]
  * = L0 / d (RGB; A written 0) and Ld[l] its 2^l x 2^l block means (App. A eq. app-pyramid),
  * Ld[l] float32 RGBA [N, H>>l, W>>l], H and W divisible by 2^(levels-1); the filter then runs on
- * Ld.  aps_remodulate: out = d * in (RGB), in and out float32 RGBA [N,H,W]; out may alias in. */
+ * Ld.  aps_remodulate: out = d * in (RGB), in and out float32 RGBA [N,H,W]; out may alias in.
+ * It also copies the recurrent latents (Sec. 3, the shared latent feature loop) when lat_out is
+ * not NULL: lat_out float32 [N,H,W,4] = z[..., lat_offset .. lat_offset + 3] (the level-0 head's
+ * four latent channels, z_stride >= lat_offset + 4), read from the logit row the map comes
+ * from; the next frame's feature assembly warps them (aps_assemble_features_ex). */
 int aps_demodulate(const float* L0, const void* z, int z_dtype, int z_stride, int z_offset, int N,
                    int H, int W, int levels, float* const* Ld, void* stream);
-int aps_remodulate(const float* in, const void* z, int z_dtype, int z_stride, int z_offset, int N,
-                   int H, int W, float* out, void* stream);
+int aps_remodulate(const float* in, const void* z, int z_dtype, int z_stride, int z_offset,
+                   int lat_offset, int N, int H, int W, float* out, float* lat_out, void* stream);
 
 /* ---------------------------------------------------------------- a10: backward passes
  * All gradients are float32 unless a dtype argument says otherwise.  "Written" outputs are
@@ -351,6 +363,13 @@ int aps_normalize_density_bwd(const float* z, int N, int H, int W, float budget_
 int aps_assemble_features_bwd(int kind, const float* L0, const float* prev, const float* mv,
                               int N, int H, int W, int C, int feat_dtype, const void* grad_feat,
                               float* grad_L0, float* grad_s, float* grad_prev, void* stream);
+/* Backward of aps_assemble_features_ex: has_lat says whether the features carried latents;
+ * grad_lat float32 [N,H,W,4] (nullable) receives their gradient through the warp (float
+ * atomics, added to). */
+int aps_assemble_features_bwd_ex(int kind, const float* L0, const float* prev, const float* mv,
+                                 int has_lat, int N, int H, int W, int C, int feat_dtype,
+                                 const void* grad_feat, float* grad_L0, float* grad_s,
+                                 float* grad_prev, float* grad_lat, void* stream);
 
 /* Data-gradient operator of a conv layer: the same MFMA kernel with w'[ci][tap][co] =
  * w[co][k*k-1-tap][ci].  packed holds aps_conv_packed_elems(Cin, ksize, Cout) elements. */

@@ -43,19 +43,25 @@ def _assemble(cols, C):
     return torch.cat([x, out[..., x.shape[-1]:]], -1)
 
 
-def sampler_features(aux, prev=None, mv=None, C: int = 8):
+def sampler_features(aux, prev=None, mv=None, C: int = 8, lat=None):
+    """lat: the previous frame's four recurrent latents (Sec. 3: a latent space shared by the
+    sampler and the denoiser, fed forward across frames), warped like prev and appended."""
     aux = torch.as_tensor(aux, dtype=F64)
     cols = [aux[..., :7]]
     if prev is not None:
         wp = warp(torch.as_tensor(prev, dtype=F64), mv)
         cols += [tonemap_eval(wp[..., :3]), valid_from_mv(torch.as_tensor(mv, dtype=F64))]
+        if lat is not None:
+            cols += [warp(torch.as_tensor(lat, dtype=F64), mv)[..., :4]]
     return _assemble(cols, C)
 
 
-def kernel_features(aux, L0, s, prev=None, mv=None, C: int = 16):
+def kernel_features(aux, L0, s, prev=None, mv=None, C: int = 16, lat=None):
     aux = torch.as_tensor(aux, dtype=F64)
     cols = [aux[..., :7], slog1p(L0[..., :3]), s]
     if prev is not None:
         wp = warp(prev, mv)
         cols += [slog1p(wp[..., :3]), valid_from_mv(torch.as_tensor(mv, dtype=F64))]
+        if lat is not None:
+            cols += [warp(torch.as_tensor(lat, dtype=F64), mv)[..., :4]]
     return _assemble(cols, C)

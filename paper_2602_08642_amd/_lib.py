@@ -43,7 +43,7 @@ SIGNATURES = {
     "aps_density_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, F, F, P, P, P, SZ, P, P]),
     "aps_avgpool2": (I, [P, I, I, I, I, I, P, P]),
     "aps_demodulate": (I, [P, P, I, I, I, I, I, I, I, P, P]),
-    "aps_remodulate": (I, [P, P, I, I, I, I, I, I, P, P]),
+    "aps_remodulate": (I, [P, P, I, I, I, I, I, I, I, P, P, P]),
     "aps_demodulate_bwd": (I, [P, P, I, I, I, I, I, I, I, P, P, P, I, P]),
     "aps_remodulate_bwd": (I, [P, P, I, I, I, I, I, I, P, P, P, I, P]),
     "aps_upsample_nearest2": (I, [P, I, I, I, P, P]),
@@ -54,6 +54,7 @@ SIGNATURES = {
     "aps_scatter_samples": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P]),
     "aps_scatter_samples_ex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P]),
     "aps_assemble_features": (I, [I, P, P, P, P, P, I, I, I, I, I, P, P]),
+    "aps_assemble_features_ex": (I, [I, P, P, P, P, P, P, I, I, I, I, I, P, P]),
     "aps_kernel_predict_workspace_size": (SZ, [C.POINTER(NetDesc), I, I, I]),
     "aps_kernel_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, I, P, I, P, P, SZ, P]),
     "aps_denoise_pyramid_workspace_size": (SZ, [I, I, I, I]),
@@ -69,6 +70,7 @@ SIGNATURES = {
     "aps_normalize_bwd_workspace_size": (SZ, [I, I, I]),
     "aps_normalize_density_bwd": (I, [P, I, I, I, F, F, P, P, P, SZ, P]),
     "aps_assemble_features_bwd": (I, [I, P, P, P, I, I, I, I, I, P, P, P, P, P]),
+    "aps_assemble_features_bwd_ex": (I, [I, P, P, P, I, I, I, I, I, I, P, P, P, P, P, P]),
     "aps_conv_pack_weights_dgrad": (I, [P, I, I, I, I, P, P]),
     "aps_conv2d_bwd_data": (I, [P, P, I, I, I, I, I, P, I, I, I, P, P]),
     "aps_conv_input_grad": (I, [I, P, I, I, I, I, I, I, P, I, P, I, P]),

@@ -66,15 +66,26 @@ __global__ __launch_bounds__(256) void k_demodulate(const float4* __restrict__ L
   }
 }
 
-// in and out may be the same buffer: each thread reads and writes only its own pixel
+// in and out may be the same buffer: each thread reads and writes only its own pixel.  With
+// lat_offset >= 0 the four latent channels of the same logit row are copied to lat (float4).
 __global__ __launch_bounds__(256) void k_remodulate(const float4* in, ZRef z, size_t npix,
-                                                    float4* out) {
+                                                    float4* out, int lat_offset,
+                                                    float4* __restrict__ lat) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= npix) return;
   float zv[3], live;
   load_z(z, i, zv);
   const float4 v = in[i];
   out[i] = make_float4(v.x * dmap(zv[0], live), v.y * dmap(zv[1], live), v.z * dmap(zv[2], live), 0.f);
+  if (lat) {
+    const size_t o = i * (size_t)z.stride + lat_offset;
+    float t[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      t[c] = z.dtype == APS_BF16 ? bf2f(static_cast<const uint16_t*>(z.p)[o + c])
+                                 : static_cast<const float*>(z.p)[o + c];
+    lat[i] = make_float4(t[0], t[1], t[2], t[3]);
+  }
 }
 
 struct GradPtrs {
@@ -180,17 +191,18 @@ int aps_demodulate(const float* L0, const void* z, int z_dtype, int z_stride, in
   return APS_OK;
 }
 
-int aps_remodulate(const float* in, const void* z, int z_dtype, int z_stride, int z_offset, int N,
-                   int H, int W, float* out, void* stream) {
+int aps_remodulate(const float* in, const void* z, int z_dtype, int z_stride, int z_offset,
+                   int lat_offset, int N, int H, int W, float* out, float* lat_out, void* stream) {
   if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
   const int zr = check_z(z_dtype, z_stride, z_offset);
   if (zr != APS_OK) return zr;
+  if (lat_out && (lat_offset < 0 || z_stride < lat_offset + 4)) return APS_ERR_SHAPE;
   const size_t npix = (size_t)N * H * W;
   if (npix == 0) return APS_OK;
   if (!in || !z || !out) return APS_ERR_NULL;
   k_remodulate<<<(unsigned)((npix + 255) / 256), 256, 0, as_stream(stream)>>>(
       reinterpret_cast<const float4*>(in), ZRef{z, z_dtype, z_stride, z_offset}, npix,
-      reinterpret_cast<float4*>(out));
+      reinterpret_cast<float4*>(out), lat_offset, reinterpret_cast<float4*>(lat_out));
   APS_LAUNCH_CHECK();
   return APS_OK;
 }

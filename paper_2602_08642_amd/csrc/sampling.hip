@@ -333,12 +333,30 @@ __device__ inline float4 warp_sample(const float4* __restrict__ prev, int H, int
                      gy * (gx * a.z + fx * b.z) + fy * (gx * c.z + fx * d.z), 0.f);
 }
 
+// all four channels (the recurrent latents use the A channel as well)
+__device__ inline float4 warp_sample4(const float4* __restrict__ src, int H, int W, int n, int x,
+                                      int y, float2 mv) {
+  const float fxf = floorf(mv.x), fyf = floorf(mv.y);
+  const float fx = mv.x - fxf, fy = mv.y - fyf;
+  const int x0 = x + (int)fxf, y0 = y + (int)fyf;
+  const int xa = min(max(x0, 0), W - 1), xb = min(max(x0 + 1, 0), W - 1);
+  const int ya = min(max(y0, 0), H - 1), yb = min(max(y0 + 1, 0), H - 1);
+  const float4* P = src + (size_t)n * H * W;
+  const float4 a = P[(size_t)ya * W + xa], b = P[(size_t)ya * W + xb];
+  const float4 c = P[(size_t)yb * W + xa], d = P[(size_t)yb * W + xb];
+  const float gx = 1.f - fx, gy = 1.f - fy;
+  return make_float4(gy * (gx * a.x + fx * b.x) + fy * (gx * c.x + fx * d.x),
+                     gy * (gx * a.y + fx * b.y) + fy * (gx * c.y + fx * d.y),
+                     gy * (gx * a.z + fx * b.z) + fy * (gx * c.z + fx * d.z),
+                     gy * (gx * a.w + fx * b.w) + fy * (gx * c.w + fx * d.w));
+}
+
 __device__ inline float mv_valid(int H, int W, int x, int y, float2 mv) {
   const float px = (float)x + mv.x, py = (float)y + mv.y;
   return (px >= -0.5f && px <= (float)W - 0.5f && py >= -0.5f && py <= (float)H - 0.5f) ? 1.f : 0.f;
 }
 
-// One pixel's feature row of C (8 or 16) channels as 16-byte stores.
+// One pixel's feature row of C (8, 16 or 24) channels as 16-byte stores.
 template <typename T>
 __device__ inline void store_row(T* dst, int C, const float* f);
 template <>
@@ -346,9 +364,13 @@ __device__ inline void store_row<float>(float* dst, int C, const float* f) {
   float4* d = reinterpret_cast<float4*>(dst);
   d[0] = make_float4(f[0], f[1], f[2], f[3]);
   d[1] = make_float4(f[4], f[5], f[6], f[7]);
-  if (C == 16) {
+  if (C >= 16) {
     d[2] = make_float4(f[8], f[9], f[10], f[11]);
     d[3] = make_float4(f[12], f[13], f[14], f[15]);
+  }
+  if (C == 24) {
+    d[4] = make_float4(f[16], f[17], f[18], f[19]);
+    d[5] = make_float4(f[20], f[21], f[22], f[23]);
   }
 }
 template <>
@@ -356,28 +378,33 @@ __device__ inline void store_row<uint16_t>(uint16_t* dst, int C, const float* f)
   u16x8* d = reinterpret_cast<u16x8*>(dst);
   d[0] = u16x8{f2bf(f[0]), f2bf(f[1]), f2bf(f[2]), f2bf(f[3]),
                f2bf(f[4]), f2bf(f[5]), f2bf(f[6]), f2bf(f[7])};
-  if (C == 16)
+  if (C >= 16)
     d[1] = u16x8{f2bf(f[8]), f2bf(f[9]), f2bf(f[10]), f2bf(f[11]),
                  f2bf(f[12]), f2bf(f[13]), f2bf(f[14]), f2bf(f[15])};
+  if (C == 24)
+    d[2] = u16x8{f2bf(f[16]), f2bf(f[17]), f2bf(f[18]), f2bf(f[19]),
+                 f2bf(f[20]), f2bf(f[21]), f2bf(f[22]), f2bf(f[23])};
 }
 
 // kind 0 (sampler input):   aux[0..6], then (temporal) tonemap(W prev) 3, valid 1; zero pad.
 // kind 1 (kernel predictor): aux[0..6], slog1p(L0) 3, s 1, then (temporal) slog1p(W prev) 3,
 //                            valid 1; zero pad.
+// Both then (recurrent latents) the 4 channels of W lat, the previous frame's latents warped.
 template <typename T>
 __global__ __launch_bounds__(256) void k_features(int kind, const float* __restrict__ aux,
                                                   const float4* __restrict__ L0,
                                                   const float* __restrict__ s,
                                                   const float4* __restrict__ prev,
-                                                  const float2* __restrict__ mv, int N, int H,
+                                                  const float2* __restrict__ mv,
+                                                  const float4* __restrict__ lat, int N, int H,
                                                   int W, int C, T* __restrict__ out) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t npix = (size_t)N * H * W;
   if (i >= npix) return;
   const int x = (int)(i % W), y = (int)((i / W) % H), n = (int)(i / ((size_t)W * H));
-  float f[16];
+  float f[24];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) f[c] = 0.f;
+  for (int c = 0; c < 24; ++c) f[c] = 0.f;
   {
     const float4 a0 = reinterpret_cast<const float4*>(aux)[2 * i];
     const float4 a1 = reinterpret_cast<const float4*>(aux)[2 * i + 1];
@@ -406,6 +433,13 @@ __global__ __launch_bounds__(256) void k_features(int kind, const float* __restr
       f[o + 2] = slog1p(w.z);
     }
     f[o + 3] = mv_valid(H, W, x, y, m);
+    if (lat) {
+      const float4 v = warp_sample4(lat, H, W, n, x, y, m);
+      f[o + 4] = v.x;
+      f[o + 5] = v.y;
+      f[o + 6] = v.z;
+      f[o + 7] = v.w;
+    }
   }
   store_row<T>(out + i * C, C, f);
 }
@@ -560,7 +594,8 @@ __device__ inline float dtonemap_eval(float L) {
 }
 
 __device__ inline void splat_prev(float* __restrict__ gprev, int H, int W, int n, int x, int y,
-                                  float2 m, float gx_, float gy_, float gz_) {
+                                  float2 m, float gx_, float gy_, float gz_, float gw_ = 0.f,
+                                  bool four = false) {
   const float fxf = floorf(m.x), fyf = floorf(m.y);
   const float fx = m.x - fxf, fy = m.y - fyf, gx = 1.f - fx, gy = 1.f - fy;
   const int x0 = x + (int)fxf, y0 = y + (int)fyf;
@@ -576,6 +611,7 @@ __device__ inline void splat_prev(float* __restrict__ gprev, int H, int W, int n
     atomicAdd(d + 0, wt[k] * gx_);
     atomicAdd(d + 1, wt[k] * gy_);
     atomicAdd(d + 2, wt[k] * gz_);
+    if (four) atomicAdd(d + 3, wt[k] * gw_);
   }
 }
 
@@ -594,7 +630,8 @@ __global__ __launch_bounds__(256) void k_features_bwd(int kind, const float4* __
                                                       int W, int C, const T* __restrict__ gfeat,
                                                       float4* __restrict__ gL0,
                                                       float* __restrict__ gs,
-                                                      float* __restrict__ gprev) {
+                                                      float* __restrict__ gprev,
+                                                      float* __restrict__ glat) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (size_t)N * H * W) return;
   const int x = (int)(i % W), y = (int)((i / W) % H), n = (int)(i / ((size_t)W * H));
@@ -627,6 +664,10 @@ __global__ __launch_bounds__(256) void k_features_bwd(int kind, const float4* __
     }
     splat_prev(gprev, H, W, n, x, y, m, load_feat<T>(g, o) * d0, load_feat<T>(g, o + 1) * d1,
                load_feat<T>(g, o + 2) * d2);
+  }
+  if (glat && mv) {  // the latents enter linearly through the warp
+    splat_prev(glat, H, W, n, x, y, mv[i], load_feat<T>(g, o + 4), load_feat<T>(g, o + 5),
+               load_feat<T>(g, o + 6), load_feat<T>(g, o + 7), true);
   }
 }
 
@@ -775,14 +816,22 @@ int aps_scatter_samples_ex(const float* s, const uint8_t* count, const int32_t* 
 int aps_assemble_features(int kind, const float* aux, const float* L0, const float* s,
                           const float* prev, const float* mv, int N, int H, int W, int C,
                           int out_dtype, void* out, void* stream) {
+  return aps_assemble_features_ex(kind, aux, L0, s, prev, mv, nullptr, N, H, W, C, out_dtype, out,
+                                  stream);
+}
+
+int aps_assemble_features_ex(int kind, const float* aux, const float* L0, const float* s,
+                             const float* prev, const float* mv, const float* lat, int N, int H,
+                             int W, int C, int out_dtype, void* out, void* stream) {
   if (kind != APS_FEAT_SAMPLER && kind != APS_FEAT_KERNEL) return APS_ERR_ARG;
   if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
   if ((size_t)N * H * W == 0) return APS_OK;
   if (!aux || !out) return APS_ERR_NULL;
   if (kind == APS_FEAT_KERNEL && (!L0 || !s)) return APS_ERR_NULL;
   if (prev && !mv) return APS_ERR_NULL;
-  const int need = (kind == APS_FEAT_KERNEL ? 11 : 7) + (prev ? 4 : 0);
-  if (C < need || (C != 8 && C != 16)) return APS_ERR_SHAPE;  // rows are 16-byte vectors
+  if (lat && !prev) return APS_ERR_NULL;
+  const int need = (kind == APS_FEAT_KERNEL ? 11 : 7) + (prev ? 4 : 0) + (lat ? 4 : 0);
+  if (C < need || (C != 8 && C != 16 && C != 24)) return APS_ERR_SHAPE;  // 16-byte row vectors
   const size_t npix = (size_t)N * H * W;
   if (npix == 0) return APS_OK;
   const int blocks = (int)((npix + 255) / 256);
@@ -790,11 +839,12 @@ int aps_assemble_features(int kind, const float* aux, const float* L0, const flo
   const float4* L4 = reinterpret_cast<const float4*>(L0);
   const float4* P4 = reinterpret_cast<const float4*>(prev);
   const float2* M2 = reinterpret_cast<const float2*>(mv);
+  const float4* T4 = reinterpret_cast<const float4*>(lat);
   if (out_dtype == APS_F32)
-    k_features<float><<<blocks, 256, 0, st>>>(kind, aux, L4, s, P4, M2, N, H, W, C,
+    k_features<float><<<blocks, 256, 0, st>>>(kind, aux, L4, s, P4, M2, T4, N, H, W, C,
                                               static_cast<float*>(out));
   else if (out_dtype == APS_BF16)
-    k_features<uint16_t><<<blocks, 256, 0, st>>>(kind, aux, L4, s, P4, M2, N, H, W, C,
+    k_features<uint16_t><<<blocks, 256, 0, st>>>(kind, aux, L4, s, P4, M2, T4, N, H, W, C,
                                                  static_cast<uint16_t*>(out));
   else
     return APS_ERR_UNSUPPORTED;
@@ -895,14 +945,24 @@ int aps_normalize_density_bwd(const float* z, int N, int H, int W, float budget_
 int aps_assemble_features_bwd(int kind, const float* L0, const float* prev, const float* mv,
                               int N, int H, int W, int C, int feat_dtype, const void* grad_feat,
                               float* grad_L0, float* grad_s, float* grad_prev, void* stream) {
+  return aps_assemble_features_bwd_ex(kind, L0, prev, mv, 0, N, H, W, C, feat_dtype, grad_feat,
+                                      grad_L0, grad_s, grad_prev, nullptr, stream);
+}
+
+int aps_assemble_features_bwd_ex(int kind, const float* L0, const float* prev, const float* mv,
+                                 int has_lat, int N, int H, int W, int C, int feat_dtype,
+                                 const void* grad_feat, float* grad_L0, float* grad_s,
+                                 float* grad_prev, float* grad_lat, void* stream) {
   if (kind != APS_FEAT_SAMPLER && kind != APS_FEAT_KERNEL) return APS_ERR_ARG;
   if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
   if ((size_t)N * H * W == 0) return APS_OK;
   if (!grad_feat) return APS_ERR_NULL;
   if (kind == APS_FEAT_KERNEL && !L0) return APS_ERR_NULL;
   if (prev && !mv) return APS_ERR_NULL;
-  const int need = (kind == APS_FEAT_KERNEL ? 11 : 7) + (prev ? 4 : 0);
-  if (C < need || C > 16) return APS_ERR_SHAPE;
+  if (has_lat && !mv) return APS_ERR_NULL;
+  const int need = (kind == APS_FEAT_KERNEL ? 11 : 7) + (prev ? 4 : 0) + (has_lat ? 4 : 0);
+  if (C < need || C > 24) return APS_ERR_SHAPE;
+  if (!has_lat) grad_lat = nullptr;
   const size_t npix = (size_t)N * H * W;
   const unsigned blocks = (unsigned)((npix + 255) / 256);
   hipStream_t st = as_stream(stream);
@@ -913,11 +973,11 @@ int aps_assemble_features_bwd(int kind, const float* L0, const float* prev, cons
   if (feat_dtype == APS_F32)
     k_features_bwd<float><<<blocks, 256, 0, st>>>(kind, L4, P4, M2, N, H, W, C,
                                                   static_cast<const float*>(grad_feat), G4, grad_s,
-                                                  grad_prev);
+                                                  grad_prev, grad_lat);
   else if (feat_dtype == APS_BF16)
     k_features_bwd<uint16_t><<<blocks, 256, 0, st>>>(kind, L4, P4, M2, N, H, W, C,
                                                      static_cast<const uint16_t*>(grad_feat), G4,
-                                                     grad_s, grad_prev);
+                                                     grad_s, grad_prev, grad_lat);
   else
     return APS_ERR_UNSUPPORTED;
   APS_LAUNCH_CHECK();

@@ -161,13 +161,16 @@ def scatter_samples(s, count, pixel_offset, samples, levels: int, mode: str = "h
 
 
 def assemble_features(kind: str, aux, L0=None, s=None, prev=None, mv=None, C_out: int = 16,
-                      dtype=_F32):
+                      dtype=_F32, lat=None):
+    """lat: the previous frame's recurrent latents [N,H,W,4] (warped and appended)."""
     _need(aux, "aux", _F32)
+    if lat is not None:
+        _need(lat, "lat", _F32)
     N, H, W, _ = aux.shape
     out = torch.empty((N, H, W, C_out), dtype=dtype, device=aux.device)
     k = L.APS_FEAT_SAMPLER if kind == "sampler" else L.APS_FEAT_KERNEL
-    L.check(L.load().aps_assemble_features(k, _p(aux), _p(L0), _p(s), _p(prev), _p(mv), N, H, W,
-                                           C_out, _dt(dtype), _p(out), _stream()),
+    L.check(L.load().aps_assemble_features_ex(k, _p(aux), _p(L0), _p(s), _p(prev), _p(mv), _p(lat),
+                                              N, H, W, C_out, _dt(dtype), _p(out), _stream()),
             "assemble_features")
     return out
 
@@ -288,13 +291,16 @@ def demodulate(L0, z0, z_offset: int, levels: int):
     return Ld
 
 
-def remodulate(x, z0, z_offset: int, out=None):
+def remodulate(x, z0, z_offset: int, out=None, lat_offset: int = -1, lat_out=None):
+    """out = x * exp(z); with lat_out, also copies z0[..., lat_offset:lat_offset+4] (latents)."""
     _need(x, "x", _F32)
     _need(z0, "z0")
     N, H, W, _ = x.shape
     out = torch.empty_like(x) if out is None else out
-    L.check(L.load().aps_remodulate(_p(x), _p(z0), _dt(z0.dtype), z0.shape[-1], z_offset, N, H, W,
-                                    _p(out), _stream()), "remodulate")
+    if lat_out is not None:
+        _need(lat_out, "lat_out", _F32)
+    L.check(L.load().aps_remodulate(_p(x), _p(z0), _dt(z0.dtype), z0.shape[-1], z_offset, lat_offset,
+                                    N, H, W, _p(out), _p(lat_out), _stream()), "remodulate")
     return out
 
 
@@ -452,13 +458,13 @@ def normalize_density_bwd(z, budget, grad_s, uniform_frac=1.0 / 8.0):
 
 
 def assemble_features_bwd(kind, grad_feat, L0=None, prev=None, mv=None, grad_L0=None,
-                          grad_s=None, grad_prev=None):
+                          grad_s=None, grad_prev=None, has_lat=False, grad_lat=None):
     _need(grad_feat, "grad_feat")
     N, H, W, Cf = grad_feat.shape
     k = L.APS_FEAT_SAMPLER if kind == "sampler" else L.APS_FEAT_KERNEL
-    L.check(L.load().aps_assemble_features_bwd(k, _p(L0), _p(prev), _p(mv), N, H, W, Cf,
-                                               _dt(grad_feat.dtype), _p(grad_feat), _p(grad_L0),
-                                               _p(grad_s), _p(grad_prev), _stream()),
+    L.check(L.load().aps_assemble_features_bwd_ex(k, _p(L0), _p(prev), _p(mv), int(has_lat), N, H, W,
+                                                  Cf, _dt(grad_feat.dtype), _p(grad_feat), _p(grad_L0),
+                                                  _p(grad_s), _p(grad_prev), _p(grad_lat), _stream()),
             "assemble_features_bwd")
 
 

@@ -34,6 +34,7 @@ class FrameConfig:
     density_scale: int = 1            # 2: sampler at a quarter of the pixels (Sec. 7)
     u_noise: str = "philox"           # u of the mask: "philox" or "blue" (void-and-cluster texture)
     demod: bool = False               # learned demodulation (Sec. 6.2): 3 more level-0 head channels
+    latents: int = 0                  # recurrent latents shared by both networks (Sec. 3): 0 or 4
 
     @property
     def sampler_cin(self) -> int:
@@ -41,7 +42,7 @@ class FrameConfig:
 
     @property
     def kernel_cin(self) -> int:
-        return 16
+        return 24 if self.latents else 16
 
     def filter_channels(self):
         """Kernel logits per level (the joint softmax of App. A)."""
@@ -59,6 +60,7 @@ class FrameConfig:
         out = self.filter_channels()
         if self.demod:
             out[0] += 3
+        out[0] += self.latents       # the latent channels follow (they ride with demodulation)
         return out
 
 
@@ -77,7 +79,7 @@ CONFIGS = {
     # kt 5x5 (54-way softmax at level 0), with the quarter-resolution density map of Sec. 7;
     # 1080 rows are not divisible by 2^4, so the frame is 1080p padded to 1088 rows
     "paper": FrameConfig("paper", 1088, 1920, 0.25, 5, 5, 2, 5, True, BF16, BF16, density_scale=2,
-                         u_noise="blue", demod=True),
+                         u_noise="blue", demod=True, latents=4),
 }
 
 
@@ -111,8 +113,11 @@ class FrameRenderer:
         self.knet = None
         if kernel_weights is not None:
             self.knet = ops.Net(kernel_spec(cfg), kernel_weights, cfg.net_dtype, self.device)
+        if cfg.latents and (cfg.latents != 4 or not cfg.demod or not cfg.temporal):
+            raise ValueError("recurrent latents are 4 channels and need demodulation and a temporal config")
         self._const_logits = None
         self.history = None
+        self.latent = None      # the latest frame's latents [N,H,W,4], read by the next frame
         self.u_tex = None
         if cfg.u_noise == "blue":   # a 64x64 void-and-cluster threshold texture (Sec. 6.3)
             import procgen
@@ -127,7 +132,7 @@ class FrameRenderer:
         if self.uniform:
             return torch.full((N, cfg.H, cfg.W), cfg.budget, dtype=F32, device=self.device)
         feat = ops.assemble_features("sampler", aux, prev=prev, mv=mv, C_out=cfg.sampler_cin,
-                                     dtype=cfg.net_dtype)
+                                     dtype=cfg.net_dtype, lat=self._lat(prev))
         if cfg.density_scale == 2:
             # quarter resolution: the budget per pixel is unchanged, so sum(s) stays Npx * B
             _, s_q = ops.density_predict(self.dnet, ops.avgpool2(feat), cfg.budget, cfg.uniform_frac)
@@ -152,7 +157,8 @@ class FrameRenderer:
                     torch.zeros((N, cfg.H >> l, cfg.W >> l, ops.round_kstride(ks[l], cfg.logit_dtype)),
                                 dtype=cfg.logit_dtype, device=self.device) for l in range(cfg.levels)]
             return self._const_logits
-        feat = ops.assemble_features("kernel", aux, L0, s, prev, mv, cfg.kernel_cin, cfg.net_dtype)
+        feat = ops.assemble_features("kernel", aux, L0, s, prev, mv, cfg.kernel_cin, cfg.net_dtype,
+                                     lat=self._lat(prev))
         if cfg.kernel_net == "cnn3":
             h = feat
             for l in self.knet.spec:
@@ -175,6 +181,12 @@ class FrameRenderer:
         out, self.history = self.filter(Ls, z, hist, use_mv, want_history=True)
         return out, Ls, z
 
+    def _lat(self, prev):
+        """The previous frame's latents, when there is a previous frame."""
+        if not self.cfg.latents or prev is None or self.latent is None:
+            return None
+        return self.latent
+
     def filter(self, Ls, z, history=None, mv=None, want_history=False):
         """Gathering pyramid.  With learned demodulation the pyramid of L0 / d is filtered and the
         result multiplied by d (d from the level-0 head channels after the kernel logits); the
@@ -185,7 +197,13 @@ class FrameRenderer:
             k0 = cfg.filter_channels()[0]
             Ld = ops.demodulate(Ls[0], z[0], k0, cfg.levels)
             out_d = ops.denoise_pyramid(Ld, z, cfg.KD, cfg.KU, cfg.KT, history, mv)
-            out = ops.remodulate(out_d, z[0], k0)
+            lat = None
+            if cfg.latents:   # copied from the level-0 logit rows the map is read from
+                N, H, W, _ = out_d.shape
+                lat = torch.empty((N, H, W, 4), dtype=F32, device=out_d.device)
+            out = ops.remodulate(out_d, z[0], k0, lat_offset=k0 + 3, lat_out=lat)
+            if lat is not None:
+                self.latent = lat
             return (out, out_d) if want_history else out
         out = ops.denoise_pyramid(Ls, z, cfg.KD, cfg.KU, cfg.KT, history, mv)
         return (out, out) if want_history else out

@@ -152,6 +152,8 @@ def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relax
     """One frame with autograd.  prev: the previous output (network inputs); history: the filter's
     temporal input (prev when None; with learned demodulation the previous demodulated
     reconstruction, which want_history returns as a third value)."""
+    if cfg.latents:
+        raise NotImplementedError("training with recurrent latents is not wired here")
     N = aux.shape[0]
     if uniform or dnet is None:
         s = torch.full((N, cfg.H, cfg.W), cfg.budget, dtype=F32, device=aux.device)

@@ -85,7 +85,7 @@ def test_zero_map_leaves_the_frame_unchanged(ops):
     reconstruction bit for bit."""
     from paper_2602_08642_amd import pipeline
     cfg = dataclasses.replace(pipeline.CONFIGS["paper"], H=64, W=96)
-    plain = dataclasses.replace(cfg, demod=False)
+    plain = dataclasses.replace(cfg, demod=False, latents=0)
     r_d = pipeline.FrameRenderer(cfg, None, None, DEV, uniform=True)
     r_p = pipeline.FrameRenderer(plain, None, None, DEV, uniform=True)
     g = torch.Generator().manual_seed(12)
@@ -119,3 +119,70 @@ def test_demod_channel_bounds(ops):
         ops.demodulate(L0, z0, 54, 1)               # channels 54..56 run past the stride
     ops.demodulate(L0, z0, 53, 1)
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ recurrent latents
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("kind,C", [("sampler", 16), ("kernel", 24)])
+def test_features_with_latents_match_oracle(ops, kind, C, dtype):
+    from oracle import features as ofeat
+    g = torch.Generator().manual_seed(21)
+    N, H, W = 2, 20, 28
+    aux = torch.rand(N, H, W, 8, generator=g)
+    L0 = torch.randn(N, H, W, 4, generator=g)
+    s = torch.rand(N, H, W, generator=g) + 0.1
+    prev = torch.rand(N, H, W, 4, generator=g) * 3
+    mv = torch.rand(N, H, W, 2, generator=g) * 8 - 4
+    lat = torch.randn(N, H, W, 4, generator=g)
+    d = lambda t: t.to(DEV)
+    if kind == "sampler":
+        f = ops.assemble_features("sampler", d(aux), prev=d(prev), mv=d(mv), C_out=C, dtype=dtype, lat=d(lat))
+        ref = ofeat.sampler_features(aux, prev, mv, C, lat=lat)
+    else:
+        f = ops.assemble_features("kernel", d(aux), d(L0), d(s), d(prev), d(mv), C, dtype, lat=d(lat))
+        ref = ofeat.kernel_features(aux, L0.double(), s.double(), prev.double(), mv, C, lat=lat)
+    tol = 1e-5 if dtype == torch.float32 else 8e-3
+    assert torch.allclose(f.double().cpu(), ref, rtol=tol, atol=tol)
+    # backward through the warped latents
+    gf = torch.randn(N, H, W, C, generator=g).to(dtype)
+    glat = torch.zeros(N, H, W, 4, device=DEV)
+    gL0 = torch.zeros(N, H, W, 4, device=DEV) if kind == "kernel" else None
+    gs = torch.zeros(N, H, W, device=DEV) if kind == "kernel" else None
+    ops.assemble_features_bwd(kind, d(gf), d(L0) if kind == "kernel" else None, d(prev), d(mv),
+                              gL0, gs, None, has_lat=True, grad_lat=glat)
+    l64 = lat.double().requires_grad_(True)
+    if kind == "sampler":
+        r = ofeat.sampler_features(aux, prev, mv, C, lat=l64)
+    else:
+        r = ofeat.kernel_features(aux, L0.double(), s.double(), prev.double(), mv, C, lat=l64)
+    (r * gf.double()).sum().backward()
+    assert torch.allclose(glat.double().cpu(), l64.grad, rtol=1e-4, atol=1e-4)
+
+
+def test_remodulate_copies_latents(ops):
+    g = torch.Generator().manual_seed(22)
+    z0 = torch.randn(1, 12, 16, 64, generator=g).to(torch.bfloat16).to(DEV)
+    x = torch.randn(1, 12, 16, 4, generator=g).to(DEV)
+    lat = torch.full((1, 12, 16, 4), 7.0, device=DEV)
+    out = ops.remodulate(x, z0, 54, lat_offset=57, lat_out=lat)
+    assert torch.equal(lat, z0[..., 57:61].float())
+    assert torch.equal(out, ops.remodulate(x, z0, 54))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.bfloat16, 2e-2)])
+def test_unet_with_24_input_channels(ops, dtype, tol):
+    import procgen
+    from oracle import unet as ounet
+    heads = [61, 29, 29]
+    spec = procgen.unet_spec(24, heads)
+    w = procgen.init_weights(spec, 33)
+    net = ops.Net(spec, w, dtype, DEV)
+    x = torch.randn(1, 32, 48, 24, generator=torch.Generator().manual_seed(6))
+    x[..., 19:] = 0
+    logits = ops.kernel_predict(net, x.to(DEV).to(dtype), heads, dtype)
+    wq = {k: (torch.tensor(a).to(dtype).double(), torch.tensor(b).double()) for k, (a, b) in w.items()}
+    ref = ounet.unet_forward(x.to(dtype).double(), wq, 3)
+    for l, K in enumerate(heads):
+        e = float((logits[l][..., :K].double().cpu() - ref[l]).norm() / ref[l].norm())
+        assert e < tol, (l, e)

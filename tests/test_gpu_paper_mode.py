@@ -165,12 +165,13 @@ def test_paper_mode_frame(ops):
     from paper_2602_08642_amd import pipeline
     cfg = dataclasses.replace(pipeline.CONFIGS["paper"], H=64, W=96)
     assert cfg.filter_channels() == [54, 29, 29, 29, 25]
-    assert cfg.head_channels() == [57, 29, 29, 29, 25]          # + the demodulation map (Sec. 6.2)
+    assert cfg.head_channels() == [61, 29, 29, 29, 25]          # + demodulation map (3) + latents (4)
+    assert cfg.kernel_cin == 24 and cfg.sampler_cin == 16
     dspec, kspec = pipeline.density_spec(cfg), pipeline.kernel_spec(cfg)
     dw, kw = procgen.init_weights(dspec, 51), procgen.init_weights(kspec, 52)
     r = pipeline.FrameRenderer(cfg, dw, kw, device=DEV)
     seed, t = 77, 1
-    clip = procgen.make_clip(seed, cfg.H, cfg.W, 2)
+    clip = procgen.make_clip(seed, cfg.H, cfg.W, 3)
     fr = clip[t]
     aux = torch.tensor(fr.aux[None], device=DEV)
     prev = torch.zeros(1, cfg.H, cfg.W, 4)
@@ -217,3 +218,27 @@ def test_paper_mode_frame(ops):
     ref = odemod.remodulate(ofilt.denoise_pyramid(Ld, z64, 5, 2, 5, prev.double().cpu(), mv.double().cpu())[0], zd)
     mag = odemod.remodulate(ofilt.denoise_magnitude(Lda, z64, 5, 2, 5, prev.double().cpu(), mv.double().cpu())[0], zd)
     assert_mag_close(out[..., :3], ref[..., :3], mag[..., :3], 2e-5, what="paper frame")
+    # the recurrent latents of this frame are the level-0 head's four channels after the map
+    assert torch.equal(r.latent, logits[0][..., 57:61].float())
+    # next frame: both networks see them warped along the new motion vectors
+    from oracle import features as ofeat
+    fr2 = clip[2]
+    aux2 = torch.tensor(fr2.aux[None], device=DEV)
+    mv2 = torch.tensor(fr2.mv[None], device=DEV)
+    lat1 = r.latent.clone()
+    fs = ops.assemble_features("sampler", aux2, prev=out, mv=mv2, C_out=16, dtype=dt, lat=r._lat(out))
+    fs_ref = ofeat.sampler_features(aux2.double().cpu(), out.double().cpu(), mv2.double().cpu(), 16,
+                                    lat=lat1.double().cpu())
+    assert torch.allclose(fs.double().cpu(), fs_ref, rtol=8e-3, atol=8e-3)
+    s2 = r.density(aux2, out, mv2)
+    zq2, sq2 = ops.density_predict(r.dnet, ops.avgpool2(fs), cfg.budget)
+    assert torch.equal(s2, ops.upsample_nearest2(sq2))
+    req2 = r.request(s2, seed, 2)
+    smp2 = ops.fixture_render(torch.tensor(procgen.sample_pool(fr2.truth, seed, 2, 8), device=DEV),
+                              req2["count"], req2["pixel_offset"], req2["capacity"])
+    out2, Ls2, logits2 = r.reconstruct(aux2, s2, req2, smp2, seed, 2, out, mv2, history=r.history)
+    kf2 = ops.assemble_features("kernel", aux2, Ls2[0], s2, out, mv2, 24, dt, lat=lat1)
+    kf2_ref = ofeat.kernel_features(aux2.double().cpu(), Ls2[0].double().cpu(), s2.double().cpu(),
+                                    out.double().cpu(), mv2.double().cpu(), 24, lat=lat1.double().cpu())
+    assert torch.allclose(kf2.double().cpu(), kf2_ref, rtol=8e-3, atol=8e-3)
+    assert torch.isfinite(out2).all() and not torch.equal(r.latent, lat1)
