@@ -84,11 +84,16 @@ class Normalize(torch.autograd.Function):
 
 
 class Scatter(torch.autograd.Function):
+    """The s-normalised scatter with the estimator of `mode` (hard, relaxed, straight_through,
+    gumbel with temperature tau, dasr with the reference radiance L_ref for its surrogate)."""
+
     @staticmethod
-    def forward(ctx, s, req: dict, samples, levels: int, mode: str, lam: float, seed: int, frame: int):
+    def forward(ctx, s, req: dict, samples, levels: int, mode: str, lam: float, seed: int, frame: int,
+                tau: float = 0.5, L_ref=None):
         Ls = ops.scatter_samples(s, req["count"], req["pixel_offset"], samples, levels, mode, lam,
-                                 seed, frame)
-        ctx.req, ctx.mode, ctx.lam, ctx.seed, ctx.frame = req, mode, lam, seed, frame
+                                 seed, frame, tau=tau)
+        ctx.req, ctx.mode, ctx.lam, ctx.seed, ctx.frame, ctx.tau = req, mode, lam, seed, frame, tau
+        ctx.L_ref = L_ref
         ctx.save_for_backward(s, samples)
         return tuple(Ls)
 
@@ -99,8 +104,8 @@ class Scatter(torch.autograd.Function):
         g = [gl.contiguous() if gl is not None else
              torch.zeros((N, H >> l, W >> l, 4), dtype=F32, device=s.device) for l, gl in enumerate(gLs)]
         gs = ops.scatter_samples_bwd(s, ctx.req["count"], ctx.req["pixel_offset"], samples, g,
-                                     ctx.mode, ctx.lam, ctx.seed, ctx.frame)
-        return gs, None, None, None, None, None, None, None
+                                     ctx.mode, ctx.lam, ctx.seed, ctx.frame, tau=ctx.tau, L_ref=ctx.L_ref)
+        return gs, None, None, None, None, None, None, None, None, None
 
 
 class Features(torch.autograd.Function):

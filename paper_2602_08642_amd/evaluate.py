@@ -1,6 +1,7 @@
 """Learned density vs uniform sampling at equal spp, and the equal-error budget ratio.
 
     python -m paper_2602_08642_amd.evaluate --steps 300 --out results.json [--save weights.npz]
+    python -m paper_2602_08642_amd.evaluate --steps 400 --estimators relaxed,straight_through,gumbel,dasr
 
 Three reconstructions on held-out procedural clips (scene seeds disjoint from training):
   learned   sampler CNN + kernel U-Net trained jointly (relaxed stochastic rounding)
@@ -86,6 +87,29 @@ def run(steps=300, batch=4, frames=8, lr=1e-3, eval_seeds=tuple(range(10000, 100
     return res, (dnet, knet_l, knet_u)
 
 
+def compare_estimators(estimators=("relaxed", "straight_through", "gumbel", "dasr"), steps=400, batch=4,
+                       frames=8, lr=1e-3, eval_seeds=tuple(range(10000, 10008)), device="cuda",
+                       cfg_name="c4", tau=0.5, log=print):
+    """Train the learned variant (sampler + kernels) with each gradient estimator of the sampling
+    step under the same schedule, and evaluate each with its own test-time forward (the hard mask;
+    deterministic rounding for DASR) at the configuration's budget."""
+    cfg = pipeline.CONFIGS[cfg_name]
+    res = {"config": cfg_name, "H": cfg.H, "W": cfg.W, "budget": cfg.budget, "steps": steps,
+           "batch": batch, "frames": frames, "tau": tau, "estimators": {}}
+    for est in estimators:
+        t0 = time.time()
+        dnet, knet, hist = train.train(cfg, train.TrainConfig(steps=steps, batch=batch, frames=frames, lr=lr,
+                                                              estimator=est, tau=tau),
+                                       device, log=lambda m, e=est: log(f"[{e}] " + m))
+        ev = train.evaluate(cfg, dnet, knet, list(eval_seeds), frames, device,
+                            mode="dasr" if est == "dasr" else "hard")
+        ev["train_s"] = round(time.time() - t0, 1)
+        ev["loss_first_last10"] = [hist[0]["loss"], float(np.mean([h["loss"] for h in hist[-10:]]))]
+        res["estimators"][est] = ev
+        log(f"[{est}] psnr {ev['psnr']:.3f} relmse {ev['relmse']:.4f}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=300)
@@ -95,7 +119,17 @@ def main():
     ap.add_argument("--size", type=int, default=None)
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None)
+    ap.add_argument("--estimators", default=None,
+                    help="comma list (relaxed,straight_through,gumbel,dasr): train and compare them")
     a = ap.parse_args()
+    if a.estimators:
+        res = compare_estimators(tuple(a.estimators.split(",")), a.steps, a.batch, a.frames, a.lr,
+                                 log=lambda m: print(m, flush=True))
+        print(json.dumps(res))
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     res, nets = run(a.steps, a.batch, a.frames, a.lr, H=a.size, log=lambda m: print(m, flush=True))
     print(json.dumps(res))
     if a.out:

@@ -148,10 +148,13 @@ class _Gate(torch.autograd.Function):
 
 
 def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relaxed",
-                  uniform=False, lam=10.0, history=None, want_history=False):
+                  uniform=False, lam=10.0, history=None, want_history=False, tau=0.5, ref=None):
     """One frame with autograd.  prev: the previous output (network inputs); history: the filter's
     temporal input (prev when None; with learned demodulation the previous demodulated
-    reconstruction, which want_history returns as a third value)."""
+    reconstruction, which want_history returns as a third value).  mode: the sampling step's
+    estimator (hard at test time; relaxed, straight_through, gumbel or dasr in training; dasr
+    needs the reference radiance ref for its surrogate gradient and is also its own test-time
+    forward, deterministic rounding)."""
     if cfg.latents:
         raise NotImplementedError("training with recurrent latents is not wired here")
     N = aux.shape[0]
@@ -160,9 +163,11 @@ def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relax
     else:
         s = density_forward(dnet, cfg, aux, prev, mv)
     cap = int(N * cfg.H * cfg.W * (cfg.budget + 1)) + 1024
-    req = ops.sample_mask(s.detach(), seed, frame, capacity=cap)
+    req = ops.sample_mask(s.detach(), seed, frame, capacity=cap, rounding=ops.MODE_ROUNDING[mode])
     samples = ops.fixture_render(pool, req["count"], req["pixel_offset"], cap)
-    Ls = ag.Scatter.apply(s, req, samples, cfg.levels, mode, lam, seed, frame)
+    if mode == "dasr" and ref is None:
+        raise ValueError("the DASR surrogate needs the reference radiance")
+    Ls = ag.Scatter.apply(s, req, samples, cfg.levels, mode, lam, seed, frame, tau, ref)
     if knet is None:
         ks = cfg.head_channels()
         logits = [torch.zeros((N, cfg.H >> l, cfg.W >> l, ops.round_kstride(ks[l], cfg.logit_dtype)),
@@ -196,6 +201,9 @@ class TrainConfig:
     log_every: int = 10
     # one model covers a range of budgets (Sec. 6.3): B log-uniform in [lo, hi] per step
     budget_range: tuple = (0.125, 1.0)
+    # gradient estimator of the sampling step (Sec. 4.3 and the compared ones); tau for gumbel
+    estimator: str = "relaxed"
+    tau: float = 0.5
 
 
 def cosine_lr(step, total, peak):
@@ -231,8 +239,10 @@ def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, 
             hin = None if prev_h is None else (pin if prev_h is prev else _Gate.apply(prev_h, gate))
             mv = cb.mv[t] if prev is not None else None
             seed = 1_000_003 * step + t
-            out, s, out_h = frame_forward(dnet, knet, cfg_s, cb.aux[t], pin, mv, pool, seed, t, "relaxed",
-                                          uniform=tc.uniform, history=hin, want_history=True)
+            out, s, out_h = frame_forward(dnet, knet, cfg_s, cb.aux[t], pin, mv, pool, seed, t,
+                                          "relaxed" if tc.uniform else tc.estimator,
+                                          uniform=tc.uniform, history=hin, want_history=True,
+                                          tau=tc.tau, ref=cb.ref[t])
             loss = ag.TMOLoss.apply(out, pin, cb.ref[t], prev_ref, mv, cb.params)
             loss.backward(retain_graph=True)
             if gate is not None:
@@ -290,8 +300,9 @@ def psnr_tonemapped(out, ref, params):
 
 @torch.no_grad()
 def evaluate(cfg: FrameConfig, dnet, knet, seeds, frames=8, device="cuda", uniform=False,
-             budget=None, gen_seed=123):
-    """Mean tonemapped PSNR and relMSE over held-out clips, hard mask (test time)."""
+             budget=None, gen_seed=123, mode="hard"):
+    """Mean tonemapped PSNR and relMSE over held-out clips, hard mask (test time; mode "dasr":
+    deterministic rounding, the test-time forward of a DASR-trained sampler)."""
     if budget is not None:
         cfg = dataclasses.replace(cfg, budget=budget)
     cb = make_clips(seeds, cfg.H, cfg.W, frames, device, randomise_tmo=False)
@@ -302,8 +313,8 @@ def evaluate(cfg: FrameConfig, dnet, knet, seeds, frames=8, device="cuda", unifo
         pool = sample_pool(cb.ref[t], gen)
         mv = cb.mv[t] if prev is not None else None
         out, _, hist = frame_forward(None if uniform else dnet, knet, cfg, cb.aux[t], prev, mv, pool,
-                                     7_000_001 + t, t, "hard", uniform=uniform, history=hist,
-                                     want_history=True)
+                                     7_000_001 + t, t, mode, uniform=uniform, history=hist,
+                                     want_history=True, ref=cb.ref[t])
         prev = out
         ps.append(psnr_tonemapped(out, cb.ref[t], cb.params))
         r = cb.ref[t][..., :3]

@@ -103,3 +103,17 @@ def test_training_reduces_loss():
     last = np.mean([h["loss"] for h in hist[-8:]])
     assert all(np.isfinite(h["loss"]) for h in hist)
     assert last < first, (first, last)
+
+
+@pytest.mark.parametrize("estimator", ["straight_through", "gumbel", "dasr"])
+def test_training_steps_with_each_estimator(estimator):
+    """Two training steps with each compared estimator of the sampling step run through and give
+    finite losses and gradients (their kernels are checked against the oracle elsewhere)."""
+    from paper_2602_08642_amd import pipeline, train
+    cfg = dataclasses.replace(pipeline.CONFIGS["c4"], H=32, W=32)
+    dnet, knet, hist = train.train(cfg, train.TrainConfig(steps=2, batch=2, frames=2, n_train_clips=2,
+                                                          estimator=estimator, log_every=1),
+                                   DEV, log=lambda m: None)
+    assert all(np.isfinite(h["loss"]) for h in hist)
+    ev = train.evaluate(cfg, dnet, knet, [10000], 2, DEV, mode="dasr" if estimator == "dasr" else "hard")
+    assert np.isfinite(ev["psnr"])
