@@ -266,6 +266,18 @@ int aps_denoise_pyramid(const float* const* L, const void* const* logits, int lo
                         const float* prev, const float* mv, int N, int H, int W, float* out,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* The same with learned demodulation (Sec. 6.2) fused into level 0: L is the demodulated
+ * pyramid (aps_demodulate); with demod_offset >= 0, out_demod [N,H,W,4] float32 receives the
+ * reconstruction o (the next frame's filter history) and out = o * exp(clamp(z, -8, 8)) with z
+ * = logits[0][..., demod_offset .. +2] (as aps_remodulate); with lat_out (requires
+ * demod_offset >= 0) the four latent channels logits[0][..., lat_offset .. +3] are copied to
+ * lat_out [N,H,W,4] float32.  demod_offset < 0 gives aps_denoise_pyramid. */
+int aps_denoise_pyramid_ex(const float* const* L, const void* const* logits, int logit_dtype,
+                           const int* kstride, int levels, int KD, int KU, int KT,
+                           const float* prev, const float* mv, int N, int H, int W,
+                           int demod_offset, int lat_offset, float* out, float* out_demod,
+                           float* lat_out, void* ws, size_t ws_bytes, void* stream);
+
 /* accum_out += T with the level-0 joint softmax (ku block present iff has_upsample). */
 int aps_reproject(const float* prev, const float* mv, const void* logits0, int logit_dtype,
                   int kstride, int KD, int KU, int KT, int has_upsample, int N, int H, int W,

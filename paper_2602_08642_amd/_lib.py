@@ -59,6 +59,7 @@ SIGNATURES = {
     "aps_kernel_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, I, P, I, P, P, SZ, P]),
     "aps_denoise_pyramid_workspace_size": (SZ, [I, I, I, I]),
     "aps_denoise_pyramid": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, P, P, SZ, P]),
+    "aps_denoise_pyramid_ex": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, I, I, P, P, P, P, SZ, P]),
     "aps_reproject": (I, [P, P, P, I, I, I, I, I, I, I, I, I, P, P]),
     "aps_upsample": (I, [P, P, I, I, I, I, I, I, I, I, I, P, P]),
     # backward

@@ -12,6 +12,11 @@ using namespace aps::flt;
 
 namespace {
 
+__device__ inline float logit_value(float v) { return v; }
+__device__ inline float logit_value(uint16_t v) { return bf2f(v); }
+// the demodulation map d = exp(clamp(z, -8, 8)) (the same as aps_remodulate)
+__device__ inline float demod_scale(float z) { return expf(fminf(fmaxf(z, -8.f), 8.f)); }
+
 template <int KD, int KU, int KT, bool HU, bool HT, typename LT>
 __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   using G = Geo<KD, KU, KT, HU, HT>;
@@ -54,12 +59,23 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   });
   const float inv = 1.f / sum;
   float4 o = make_float4(ax * inv, ay * inv, az * inv, 0.f);
-  float4* dst = a.out + ((size_t)n * H + y) * W + x;
+  const size_t pix = ((size_t)n * H + y) * W + x;
+  float4* dst = a.out + pix;
   if (a.accumulate) {
     const float4 p = *dst;
     o.x += p.x;
     o.y += p.y;
     o.z += p.z;
+  }
+  if (a.hist) {  // remodulation, reading the map from the logit row loaded above
+    const LT* row = static_cast<const LT*>(a.logits) + pix * a.kstride;
+    a.hist[pix] = o;
+    o.x *= demod_scale(logit_value(row[a.remod]));
+    o.y *= demod_scale(logit_value(row[a.remod + 1]));
+    o.z *= demod_scale(logit_value(row[a.remod + 2]));
+    if (a.lat)
+      a.lat[pix] = make_float4(logit_value(row[a.lat_off]), logit_value(row[a.lat_off + 1]),
+                               logit_value(row[a.lat_off + 2]), logit_value(row[a.lat_off + 3]));
   }
   *dst = o;
 }
@@ -110,7 +126,18 @@ int aps_denoise_pyramid(const float* const* L, const void* const* logits, int lo
                         const int* kstride, int levels, int KD, int KU, int KT,
                         const float* prev, const float* mv, int N, int H, int W, float* out,
                         void* ws, size_t ws_bytes, void* stream) {
+  return aps_denoise_pyramid_ex(L, logits, logit_dtype, kstride, levels, KD, KU, KT, prev, mv, N, H,
+                                W, -1, -1, out, nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+int aps_denoise_pyramid_ex(const float* const* L, const void* const* logits, int logit_dtype,
+                           const int* kstride, int levels, int KD, int KU, int KT,
+                           const float* prev, const float* mv, int N, int H, int W,
+                           int demod_offset, int lat_offset, float* out, float* out_demod,
+                           float* lat_out, void* ws, size_t ws_bytes, void* stream) {
   if (levels < 1 || levels > APS_MAX_LEVELS) return APS_ERR_UNSUPPORTED;
+  if (demod_offset >= 0 && (!out_demod || kstride == nullptr)) return APS_ERR_NULL;
+  if (lat_out && (demod_offset < 0 || lat_offset < 0)) return APS_ERR_ARG;
   if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
   const int div = 1 << (levels - 1);
   if (H % div || W % div) return APS_ERR_SHAPE;
@@ -125,6 +152,8 @@ int aps_denoise_pyramid(const float* const* L, const void* const* logits, int lo
     if (!kstride_ok(kstride[l], level_k(l, levels, KD, KU, KT, temporal), logit_dtype))
       return APS_ERR_SHAPE;
   }
+  if (demod_offset >= 0 && kstride[0] < demod_offset + 3) return APS_ERR_SHAPE;
+  if (lat_out && kstride[0] < lat_offset + 4) return APS_ERR_SHAPE;
   float4* tmp[APS_MAX_LEVELS] = {};
   char* wp = static_cast<char*>(ws);
   for (int l = 1; l < levels; ++l) {
@@ -147,6 +176,12 @@ int aps_denoise_pyramid(const float* const* L, const void* const* logits, int lo
     a.eval_u = l < levels - 1;
     a.eval_t = l == 0 && temporal;
     a.accumulate = 0;
+    if (l == 0 && demod_offset >= 0) {
+      a.hist = reinterpret_cast<float4*>(out_demod);
+      a.remod = demod_offset;
+      a.lat = reinterpret_cast<float4*>(lat_out);
+      a.lat_off = lat_offset;
+    }
     const int r = launch_level(a, logit_dtype, KD, KU, KT, l < levels - 1, l == 0 && temporal,
                                N, st);
     if (r != APS_OK) return r;

@@ -19,6 +19,13 @@ struct LevelArgs {
   float4* out;           // [N, H, W]
   int H, W;
   int eval_g, eval_u, eval_t, accumulate;
+  // learned demodulation (level 0): with hist set, the reconstruction o (of the demodulated
+  // pyramid) is also written to hist and out = o * exp(clamp(z[remod .. remod + 2], -8, 8));
+  // with lat set, the four latent channels z[lat_off .. lat_off + 3] are copied to lat
+  float4* hist;
+  int remod;
+  float4* lat;
+  int lat_off;
 };
 
 // Logits are read as whole 16-byte vectors: NKP = K rounded up to 4 (f32) or 8 (bf16)

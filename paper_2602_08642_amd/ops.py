@@ -358,7 +358,10 @@ def kernel_predict(net: Net, feat, head_channels, logit_dtype=_F32):
 
 # ------------------------------------------------------------------ reconstruction (a6-a9)
 
-def denoise_pyramid(Ls, logits, KD: int, KU: int, KT: int, prev=None, mv=None):
+def denoise_pyramid(Ls, logits, KD: int, KU: int, KT: int, prev=None, mv=None, demod_offset: int = -1,
+                    lat_offset: int = -1, out_demod=None, lat_out=None):
+    """With demod_offset >= 0 (Ls demodulated): out is remodulated in the level-0 kernel, the
+    reconstruction before it goes to out_demod, and with lat_out the latents are copied."""
     levels = len(Ls)
     L0 = _need(Ls[0], "L0", _F32)
     N, H, W, _ = L0.shape
@@ -372,8 +375,9 @@ def denoise_pyramid(Ls, logits, KD: int, KU: int, KT: int, prev=None, mv=None):
     la = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in Ls])
     za = (C.c_void_p * L.APS_MAX_LEVELS)(*[t.data_ptr() for t in logits])
     ka = (C.c_int * L.APS_MAX_LEVELS)(*[t.shape[-1] for t in logits])
-    L.check(lib.aps_denoise_pyramid(la, za, _dt(ldt), ka, levels, KD, KU, KT, _p(prev), _p(mv),
-                                    N, H, W, _p(out), _p(ws), nb, _stream()), "denoise_pyramid")
+    L.check(lib.aps_denoise_pyramid_ex(la, za, _dt(ldt), ka, levels, KD, KU, KT, _p(prev), _p(mv),
+                                       N, H, W, demod_offset, lat_offset, _p(out), _p(out_demod),
+                                       _p(lat_out), _p(ws), nb, _stream()), "denoise_pyramid")
     return out
 
 

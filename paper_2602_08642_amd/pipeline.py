@@ -196,12 +196,14 @@ class FrameRenderer:
         if cfg.demod:
             k0 = cfg.filter_channels()[0]
             Ld = ops.demodulate(Ls[0], z[0], k0, cfg.levels)
-            out_d = ops.denoise_pyramid(Ld, z, cfg.KD, cfg.KU, cfg.KT, history, mv)
+            out_d = torch.empty_like(Ls[0])
             lat = None
             if cfg.latents:   # copied from the level-0 logit rows the map is read from
-                N, H, W, _ = out_d.shape
-                lat = torch.empty((N, H, W, 4), dtype=F32, device=out_d.device)
-            out = ops.remodulate(out_d, z[0], k0, lat_offset=k0 + 3, lat_out=lat)
+                lat = torch.empty_like(Ls[0])
+            # remodulation (and the latent copy) happen in the level-0 filter kernel
+            out = ops.denoise_pyramid(Ld, z, cfg.KD, cfg.KU, cfg.KT, history, mv, demod_offset=k0,
+                                      lat_offset=k0 + 3 if cfg.latents else -1, out_demod=out_d,
+                                      lat_out=lat)
             if lat is not None:
                 self.latent = lat
             return (out, out_d) if want_history else out

@@ -186,3 +186,27 @@ def test_unet_with_24_input_channels(ops, dtype, tol):
     for l, K in enumerate(heads):
         e = float((logits[l][..., :K].double().cpu() - ref[l]).norm() / ref[l].norm())
         assert e < tol, (l, e)
+
+
+def test_fused_remodulation_equals_separate_passes(ops):
+    """aps_denoise_pyramid_ex with the map's channel offset: out equals the separate filter and
+    remodulation passes bit for bit, out_demod the plain reconstruction, lat_out the latents."""
+    g = torch.Generator().manual_seed(31)
+    N, H, W, levels, KD, KU, KT = 1, 48, 64, 3, 5, 2, 5
+    from tests.test_gpu_stages import _rand_inputs
+    Ls, logits, prev, mv = _rand_inputs(N, H, W, levels, KD, KU, KT, True, 33, torch.bfloat16)
+    z0 = torch.randn(N, H, W, 64, generator=g)
+    z0[..., :logits[0].shape[-1]] = logits[0].float()
+    logits[0] = z0.to(torch.bfloat16)                 # 54 kernel logits, then the map and latents
+    d = lambda t: t.to(DEV)
+    Ld = ops.demodulate(d(Ls[0]), d(logits[0]), 54, levels)
+    zs = [d(t) for t in logits]
+    plain = ops.denoise_pyramid(Ld, zs, KD, KU, KT, d(prev), d(mv))
+    sep = ops.remodulate(plain, zs[0], 54)
+    out_d = torch.empty_like(plain)
+    lat = torch.empty_like(plain)
+    fused = ops.denoise_pyramid(Ld, zs, KD, KU, KT, d(prev), d(mv), demod_offset=54, lat_offset=57,
+                                out_demod=out_d, lat_out=lat)
+    assert torch.equal(fused, sep)
+    assert torch.equal(out_d, plain)
+    assert torch.equal(lat, zs[0][..., 57:61].float())
