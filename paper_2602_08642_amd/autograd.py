@@ -109,11 +109,15 @@ class Scatter(torch.autograd.Function):
 
 
 class Features(torch.autograd.Function):
+    """Network inputs; lat: the previous frame's recurrent latents [N,H,W,4] (optional)."""
+
     @staticmethod
-    def forward(ctx, kind: str, aux, L0, s, prev, mv, C: int, dtype):
+    def forward(ctx, kind: str, aux, L0, s, prev, mv, C: int, dtype, lat=None):
         ctx.kind = kind
+        ctx.has_lat = lat is not None
         ctx.save_for_backward(L0, prev, mv)
-        return ops.assemble_features(kind, aux, L0, s, prev, mv, C, dtype)
+        return ops.assemble_features(kind, aux, L0, s, prev, mv, C, dtype,
+                                     lat=None if lat is None else lat.contiguous())
 
     @staticmethod
     def backward(ctx, gf):
@@ -123,8 +127,11 @@ class Features(torch.autograd.Function):
         gs = (torch.zeros(gf.shape[:3], dtype=F32, device=gf.device)
               if ctx.kind == "kernel" and ctx.needs_input_grad[3] else None)
         gp = torch.zeros_like(prev) if (prev is not None and ctx.needs_input_grad[4]) else None
-        ops.assemble_features_bwd(ctx.kind, gf, L0, prev, mv, gL0, gs, gp)
-        return None, None, gL0, gs, gp, None, None, None
+        gl = (torch.zeros((*gf.shape[:3], 4), dtype=F32, device=gf.device)
+              if ctx.has_lat and ctx.needs_input_grad[8] else None)
+        ops.assemble_features_bwd(ctx.kind, gf, L0, prev, mv, gL0, gs, gp, has_lat=ctx.has_lat,
+                                  grad_lat=gl)
+        return None, None, gL0, gs, gp, None, None, None, gl
 
 
 class Denoise(torch.autograd.Function):

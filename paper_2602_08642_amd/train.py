@@ -100,10 +100,10 @@ class TrainNet:
         return {n: (lr.w.detach().cpu().numpy(), lr.b.detach().cpu().numpy()) for n, lr in self.layers.items()}
 
 
-def density_forward(net: TrainNet, cfg: FrameConfig, aux, prev, mv):
+def density_forward(net: TrainNet, cfg: FrameConfig, aux, prev, mv, lat=None):
     if cfg.density_scale != 1:
         raise NotImplementedError("training runs the sampler at full resolution")
-    feat = ag.Features.apply("sampler", aux, None, None, prev, mv, cfg.sampler_cin, cfg.net_dtype)
+    feat = ag.Features.apply("sampler", aux, None, None, prev, mv, cfg.sampler_cin, cfg.net_dtype, lat)
     L = net.layers
     h = ag.conv(feat, L["d0"])
     h = ag.conv(h, L["d1"])
@@ -148,20 +148,20 @@ class _Gate(torch.autograd.Function):
 
 
 def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relaxed",
-                  uniform=False, lam=10.0, history=None, want_history=False, tau=0.5, ref=None):
+                  uniform=False, lam=10.0, history=None, want_history=False, tau=0.5, ref=None,
+                  lat=None, want_latent=False):
     """One frame with autograd.  prev: the previous output (network inputs); history: the filter's
     temporal input (prev when None; with learned demodulation the previous demodulated
     reconstruction, which want_history returns as a third value).  mode: the sampling step's
     estimator (hard at test time; relaxed, straight_through, gumbel or dasr in training; dasr
     needs the reference radiance ref for its surrogate gradient and is also its own test-time
     forward, deterministic rounding)."""
-    if cfg.latents:
-        raise NotImplementedError("training with recurrent latents is not wired here")
     N = aux.shape[0]
+    lat_in = lat if (cfg.latents and prev is not None) else None
     if uniform or dnet is None:
         s = torch.full((N, cfg.H, cfg.W), cfg.budget, dtype=F32, device=aux.device)
     else:
-        s = density_forward(dnet, cfg, aux, prev, mv)
+        s = density_forward(dnet, cfg, aux, prev, mv, lat_in)
     cap = int(N * cfg.H * cfg.W * (cfg.budget + 1)) + 1024
     req = ops.sample_mask(s.detach(), seed, frame, capacity=cap, rounding=ops.MODE_ROUNDING[mode])
     samples = ops.fixture_render(pool, req["count"], req["pixel_offset"], cap)
@@ -173,7 +173,7 @@ def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relax
         logits = [torch.zeros((N, cfg.H >> l, cfg.W >> l, ops.round_kstride(ks[l], cfg.logit_dtype)),
                               dtype=cfg.logit_dtype, device=aux.device) for l in range(cfg.levels)]
     else:
-        feat = ag.Features.apply("kernel", aux, Ls[0], s, prev, mv, cfg.kernel_cin, cfg.net_dtype)
+        feat = ag.Features.apply("kernel", aux, Ls[0], s, prev, mv, cfg.kernel_cin, cfg.net_dtype, lat_in)
         logits = unet_forward(knet, cfg, feat)
     hist = prev if history is None else history
     if cfg.demod:
@@ -183,7 +183,11 @@ def frame_forward(dnet, knet, cfg, aux, prev, mv, pool, seed, frame, mode="relax
         out = ag.Remod.apply(out_h, logits[0], k0)
     else:
         out = out_h = ag.denoise(list(Ls), logits, cfg.KD, cfg.KU, cfg.KT, hist, mv)
-    return (out, s, out_h) if want_history else (out, s)
+    res = (out, s) + ((out_h,) if want_history else ())
+    if want_latent:   # this frame's latents: the four level-0 head channels after the map
+        k0 = cfg.filter_channels()[0] + 3
+        res += ((logits[0][..., k0:k0 + 4].float().contiguous() if cfg.latents else None),)
+    return res
 
 
 # ------------------------------------------------------------------ training
@@ -228,7 +232,7 @@ def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, 
         if ci not in data:
             data[ci] = make_clips(pool_clips[ci], cfg.H, cfg.W, tc.frames, device, rng_seed=ci)
         cb = data[ci]
-        prev, prev_h, prev_ref, gate = None, None, None, None
+        prev, prev_h, prev_lat, prev_ref, gate = None, None, None, None, None
         losses = []
         lo, hi = tc.budget_range
         bstep = float(math.exp(np.random.default_rng([tc.seed, step]).uniform(math.log(lo), math.log(hi))))
@@ -237,19 +241,20 @@ def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, 
             pool = sample_pool(cb.ref[t], gen)
             pin = None if prev is None else _Gate.apply(prev, gate)
             hin = None if prev_h is None else (pin if prev_h is prev else _Gate.apply(prev_h, gate))
+            lin = None if prev_lat is None else _Gate.apply(prev_lat, gate)
             mv = cb.mv[t] if prev is not None else None
             seed = 1_000_003 * step + t
-            out, s, out_h = frame_forward(dnet, knet, cfg_s, cb.aux[t], pin, mv, pool, seed, t,
-                                          "relaxed" if tc.uniform else tc.estimator,
-                                          uniform=tc.uniform, history=hin, want_history=True,
-                                          tau=tc.tau, ref=cb.ref[t])
+            out, s, out_h, lat = frame_forward(dnet, knet, cfg_s, cb.aux[t], pin, mv, pool, seed, t,
+                                               "relaxed" if tc.uniform else tc.estimator,
+                                               uniform=tc.uniform, history=hin, want_history=True,
+                                               tau=tc.tau, ref=cb.ref[t], lat=lin, want_latent=True)
             loss = ag.TMOLoss.apply(out, pin, cb.ref[t], prev_ref, mv, cb.params)
             loss.backward(retain_graph=True)
             if gate is not None:
                 gate["open"] = False        # frame t-2 stays out of later windows
             losses.append(loss.detach())
-            prev, prev_h, prev_ref, gate = out, out_h, cb.ref[t], {"open": True}
-        del prev, prev_h, out, out_h, loss, pin
+            prev, prev_h, prev_lat, prev_ref, gate = out, out_h, lat, cb.ref[t], {"open": True}
+        del prev, prev_h, prev_lat, out, out_h, lat, loss, pin
         # AdamW on the fp32 masters (gradients averaged over the frames)
         lr = cosine_lr(step - 1, tc.steps, tc.lr)
         gn = 0.0
@@ -307,14 +312,14 @@ def evaluate(cfg: FrameConfig, dnet, knet, seeds, frames=8, device="cuda", unifo
         cfg = dataclasses.replace(cfg, budget=budget)
     cb = make_clips(seeds, cfg.H, cfg.W, frames, device, randomise_tmo=False)
     gen = torch.Generator(device=device).manual_seed(gen_seed)
-    prev = hist = None
+    prev = hist = lat = None
     ps, rm = [], []
     for t in range(frames):
         pool = sample_pool(cb.ref[t], gen)
         mv = cb.mv[t] if prev is not None else None
-        out, _, hist = frame_forward(None if uniform else dnet, knet, cfg, cb.aux[t], prev, mv, pool,
-                                     7_000_001 + t, t, mode, uniform=uniform, history=hist,
-                                     want_history=True, ref=cb.ref[t])
+        out, _, hist, lat = frame_forward(None if uniform else dnet, knet, cfg, cb.aux[t], prev, mv, pool,
+                                          7_000_001 + t, t, mode, uniform=uniform, history=hist,
+                                          want_history=True, ref=cb.ref[t], lat=lat, want_latent=True)
         prev = out
         ps.append(psnr_tonemapped(out, cb.ref[t], cb.params))
         r = cb.ref[t][..., :3]

@@ -24,11 +24,14 @@ def _small_cfg():
                                logit_dtype=torch.float32, widths=(8, 16, 16, 16))
 
 
-@pytest.mark.parametrize("demod", [False, True])
-def test_frame_gradients_match_oracle(demod):
+@pytest.mark.parametrize("demod,latents", [(False, 0), (True, 0), (True, 4)])
+def test_frame_gradients_match_oracle(demod, latents):
+    """With latents the frame takes the previous frame's latents (a leaf with a gradient) and its
+    own latents enter the loss through a fixed random weighting, so the gradient reaches the
+    latent head channels and both networks through the warped latent inputs."""
     from paper_2602_08642_amd import autograd as ag
     from paper_2602_08642_amd import ops, pipeline, train
-    cfg = dataclasses.replace(_small_cfg(), demod=demod)
+    cfg = dataclasses.replace(_small_cfg(), demod=demod, latents=latents)
     N, H, W = 2, cfg.H, cfg.W
     dspec, kspec = pipeline.density_spec(cfg), pipeline.kernel_spec(cfg)
     dw = procgen.init_weights(dspec, 3)
@@ -41,8 +44,15 @@ def test_frame_gradients_match_oracle(demod):
     mv = cb.mv[1]
     pool = train.sample_pool(cb.ref[1], gen)
     seed, frame = 77, 1
-    out, s = train.frame_forward(dnet, knet, cfg, cb.aux[1], prev, mv, pool, seed, frame, "relaxed")
+    g = torch.Generator().manual_seed(9)
+    lat_in = torch.randn(N, H, W, 4, generator=g)
+    wlat = torch.randn(N, H, W, 4, generator=g) * 1e-3
+    lat_d = lat_in.to(DEV).requires_grad_(True) if latents else None
+    out, s, lat_out = train.frame_forward(dnet, knet, cfg, cb.aux[1], prev, mv, pool, seed, frame,
+                                          "relaxed", lat=lat_d, want_latent=True)
     loss = ag.TMOLoss.apply(out, None, cb.ref[1], None, None, cb.params)
+    if latents:
+        loss = loss + (lat_out * wlat.to(DEV)).sum()
     loss.backward()
 
     # oracle: the same frame in FP64 with the GPU's s-derived mask and samples
@@ -55,13 +65,14 @@ def test_frame_gradients_match_oracle(demod):
     dwt, kwt = tw(dw), tw(kw)
     aux = cb.aux[1].double().cpu()
     p64, m64 = prev.double().cpu(), mv.double().cpu()
-    fs = ofeat.sampler_features(aux, p64, m64, cfg.sampler_cin)
+    l64 = lat_in.double().requires_grad_(True) if latents else None
+    fs = ofeat.sampler_features(aux, p64, m64, cfg.sampler_cin, lat=l64)
     z = odens.cnn_forward(fs, [(dwt[l["name"]][0], dwt[l["name"]][1], l["relu"]) for l in dspec])[..., 0]
     s64 = odens.normalise(z, cfg.budget)
     assert np.allclose(s64.detach().numpy(), s.detach().cpu().numpy(), rtol=1e-4)
     L0 = osamp.scatter(s64, req["count"].cpu().numpy(), smp, seed, frame, "relaxed", 10.0)
     Ls = osamp.pyramid(L0, cfg.levels)
-    fk = ofeat.kernel_features(aux, L0, s64, p64, m64, cfg.kernel_cin)
+    fk = ofeat.kernel_features(aux, L0, s64, p64, m64, cfg.kernel_cin, lat=l64)
     logits = ounet.unet_forward(fk, kwt, cfg.levels)
     if demod:   # learned demodulation: the filter sees L0 / d, its output is multiplied by d
         from oracle import demod as odemod
@@ -76,8 +87,15 @@ def test_frame_gradients_match_oracle(demod):
         prm = dict(zip(["k", "alpha", "beta", "s", "h"], cb.params[n].double().cpu().tolist()))
         ltot = ltot + otmo.frame_loss(otmo.tonemap(o64[n:n + 1], prm),
                                       otmo.tonemap(cb.ref[1][n:n + 1].double().cpu(), prm)) / N
+    if latents:
+        k1 = cfg.filter_channels()[0] + 3
+        ltot = ltot + (logits[0][..., k1:k1 + 4] * wlat.double()).sum()
     ltot.backward()
     assert abs(float(loss.item()) - float(ltot)) < 1e-4 * abs(float(ltot))
+    if latents:
+        ref_g = l64.grad
+        rel = float((lat_d.grad.double().cpu() - ref_g).norm() / ref_g.norm())
+        assert rel < 2e-3, ("latent input gradient", rel)
     worst = 0.0
     for net, ref in ((knet, kwt), (dnet, dwt)):
         for name, lr in net.layers.items():
@@ -116,4 +134,19 @@ def test_training_steps_with_each_estimator(estimator):
                                    DEV, log=lambda m: None)
     assert all(np.isfinite(h["loss"]) for h in hist)
     ev = train.evaluate(cfg, dnet, knet, [10000], 2, DEV, mode="dasr" if estimator == "dasr" else "hard")
+    assert np.isfinite(ev["psnr"])
+
+
+def test_training_steps_with_demodulation_and_latents():
+    """Training through learned demodulation and the recurrent latents: the latents of frame t feed
+    frame t+1 inside the two-frame window and the run gives finite losses; the evaluation then
+    carries them across its frames."""
+    from paper_2602_08642_amd import pipeline, train
+    cfg = dataclasses.replace(pipeline.CONFIGS["c4"], H=32, W=32, demod=True, latents=4)
+    dnet, knet, hist = train.train(cfg, train.TrainConfig(steps=3, batch=2, frames=3, n_train_clips=2,
+                                                          log_every=1), DEV, log=lambda m: None)
+    assert all(np.isfinite(h["loss"]) for h in hist)
+    for name, lr in knet.layers.items():
+        assert torch.isfinite(lr.w).all(), name
+    ev = train.evaluate(cfg, dnet, knet, [10000], 3, DEV)
     assert np.isfinite(ev["psnr"])
