@@ -198,6 +198,18 @@ __device__ inline void store_out<uint16_t>(uint16_t* p, int ldy, int co0, int Co
 // Epilogue shared by the convolution kernels: bias, optional ReLU, store; with HEAD, the fused
 // 1x1 head.  acc[m][j] holds output rows row0 + j, channels 16 (cob TM + m) + 4 (lane / 16) + q,
 // pixel column tx0 + lane % 16.  Xs is the block's LDS tile, reused by the head's re-layout.
+// s_waitcnt immediate (gfx9 encoding) that waits for all vector memory operations only:
+// vmcnt = 0, expcnt = 7 and lgkmcnt = 15 (no wait on those).
+constexpr int kWaitVm0 = 0x0F70;
+
+// LDS the fused head's epilogue needs, in elements of the tile type T: per wave a [16 px][16 TM
+// ch] re-layout region (row pitch 16 TM + 8 or + 4), then per wave a [16 px][<= 64 ch] staging
+// region for the head outputs (type TO).  The kernels size their input tile at least this large.
+template <typename T, typename TO, int TM>
+constexpr int head_lds_elems() {
+  return 4 * 16 * (TM * 16 + (sizeof(T) == 2 ? 8 : 4)) + 4 * 16 * 64 * (int)(sizeof(TO) / sizeof(T));
+}
+
 template <typename T, typename TO, int TM, int TN, bool HEAD, bool BIAS_IN_ACC = false>
 __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], int row0, int tx0,
                                      int cob, int n, int lane, int wave, T* Xs) {
@@ -236,8 +248,16 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
     // B fragments and multiplies it by the packed head weights (held in registers), the same
     // operands in the same order as the stand-alone 1x1 convolution of the stored tile.  The
     // regions are per wave, so after the caller's barrier only wave-local ordering is needed.
+    // Head outputs go out through a second per-wave region: the row's [npx][hldy] run of
+    // logits is contiguous in memory, so the wave writes it with 16-byte vector stores to
+    // consecutive addresses (channels in [hK, hldy) as zeros) instead of one 8- or 16-byte piece
+    // per lane and 16-channel group at the pixel stride, which measured about twice as slow.
     constexpr int CC = TM * 16, YP = CC + (sizeof(T) == 2 ? 8 : 4);
     T* Ys = Xs + wave * 16 * YP;
+    TO* Os = reinterpret_cast<TO*>(Xs + 4 * 16 * YP) + wave * 16 * 64;
+    const bool staged = a.hldy <= 64 && (a.hldy * (int)sizeof(TO)) % 16 == 0 &&
+                        (reinterpret_cast<uintptr_t>(a.hy) & 15) == 0;
+    const int npx = a.W - tx0 < 16 ? a.W - tx0 : 16;
     const T* hw = static_cast<const T*>(a.hw);
     TO* hy = static_cast<TO*>(a.hy);
     Frag<T> hwf[4][TM / 2];
@@ -246,14 +266,20 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
 #pragma unroll
       for (int cc = 0; cc < TM / 2; ++cc)
         if (mh * 16 < a.hK) frag_load(hwf[mh][cc], hw + ((((size_t)mh * (TM / 2)) + cc) * 64 + lane) * 8);
+    // head biases: unconditional loads (index clamped to a valid entry), then one wait for them
+    // and the head weights here.  Left to the compiler, the wait for a value loaded under a
+    // branch is placed at each use inside the later (branching) store code, and as vmcnt also
+    // counts stores, every one of those waits would drain all stores issued before it.
     float hb[4][4];
 #pragma unroll
     for (int mh = 0; mh < 4; ++mh)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = mh * 16 + 4 * (lane >> 4) + q;
-        hb[mh][q] = k < a.hK ? a.hb[k] : 0.f;
+        const float v = a.hb[k < a.hK ? k : 0];
+        hb[mh][q] = k < a.hK ? v : 0.f;
       }
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int row = row0 + j;
@@ -280,18 +306,49 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
       Frag<T> bf[TM / 2];
 #pragma unroll
       for (int cc = 0; cc < TM / 2; ++cc) frag_load(bf[cc], Ys + (lane & 15) * YP + 32 * cc + 8 * (lane >> 4));
+      if (staged) {
 #pragma unroll
-      for (int mh = 0; mh < 4; ++mh) {
-        if (mh * 16 >= a.hK) break;
-        f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int mh = 0; mh < 4; ++mh) {
+          const int k0 = mh * 16 + 4 * (lane >> 4);
+          if (mh * 16 >= a.hldy) break;
+          f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
+          if (mh * 16 < a.hK) {
 #pragma unroll
-        for (int cc = 0; cc < TM / 2; ++cc) h = mma(hwf[mh][cc], bf[cc], h);
-        const int k0 = mh * 16 + 4 * (lane >> 4);
-        if (inpx && k0 < a.hK) {
+            for (int cc = 0; cc < TM / 2; ++cc) h = mma(hwf[mh][cc], bf[cc], h);
+          }
           float o[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) o[q] = h[q] + hb[mh][q];
-          store_out<TO>(hy + (((size_t)n * a.H + row) * a.W + col) * a.hldy, a.hldy, k0, a.hK, o);
+          for (int q = 0; q < 4; ++q) o[q] = k0 + q < a.hK ? h[q] + hb[mh][q] : 0.f;
+          if (k0 < a.hldy) {
+            if constexpr (sizeof(TO) == 2)
+              *reinterpret_cast<u16x4*>(Os + (lane & 15) * a.hldy + k0) = f2bf4(o[0], o[1], o[2], o[3]);
+            else
+              *reinterpret_cast<f32x4*>(Os + (lane & 15) * a.hldy + k0) = f32x4{o[0], o[1], o[2], o[3]};
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (row < a.H) {
+          const int nvec = npx * a.hldy * (int)sizeof(TO) / 16;
+          uint4* dst = reinterpret_cast<uint4*>(hy + (((size_t)n * a.H + row) * a.W + tx0) * a.hldy);
+          const uint4* src = reinterpret_cast<const uint4*>(Os);
+          for (int v = lane; v < nvec; v += 64) dst[v] = src[v];
+        }
+      } else {
+#pragma unroll
+        for (int mh = 0; mh < 4; ++mh) {
+          if (mh * 16 >= a.hK) break;
+          f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int cc = 0; cc < TM / 2; ++cc) h = mma(hwf[mh][cc], bf[cc], h);
+          const int k0 = mh * 16 + 4 * (lane >> 4);
+          if (inpx && k0 < a.hK) {
+            float o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = h[q] + hb[mh][q];
+            store_out<TO>(hy + (((size_t)n * a.H + row) * a.W + col) * a.hldy, a.hldy, k0, a.hK, o);
+          }
         }
       }
       // the next row's re-layout overwrites Ys
@@ -312,7 +369,8 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   constexpr int TH = 4 * TN, TWp = 16;
   constexpr int SW = TWp + 2 * R, SH = TH + 2 * R;
   constexpr int PS = sizeof(T) == 2 ? 40 : 36;  // padded LDS pixel stride (elements)
-  __shared__ __attribute__((aligned(16))) T Xs[SH * SW * PS];
+  constexpr int XS_HEAD = HEAD ? head_lds_elems<T, TO, TM>() : 0;
+  __shared__ __attribute__((aligned(16))) T Xs[SH * SW * PS > XS_HEAD ? SH * SW * PS : XS_HEAD];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const TileId tid_ = xcd_tile(blockIdx.x, a.ntiles, a.nco);
@@ -406,9 +464,9 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   constexpr int ROWS = 4 * TN, SH = ROWS + 2, SW = 18, PS = 40;
   constexpr int NXV = SH * SW * 4, NXT = (NXV + 255) / 256;  // input 16-B vectors per chunk
   constexpr int NAV = TM * 9 * 64, NAT = (NAV + 255) / 256;  // weight 16-B vectors per chunk
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[SH * SW * PS];
+  constexpr int XS_TILE = SH * SW * PS, XS_HEAD = HEAD ? head_lds_elems<uint16_t, uint16_t, TM>() : 0;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[XS_TILE > XS_HEAD ? XS_TILE : XS_HEAD];
   __shared__ __attribute__((aligned(16))) uint16_t As[NAV * 8];
-  static_assert(!HEAD || SH * SW * PS >= 4 * 16 * (TM * 16 + 8), "head re-layout exceeds Xs");
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const TileId tid_ = xcd_tile(blockIdx.x, a.ntiles, a.nco);
@@ -679,8 +737,8 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds_f32(ConvArgs a) {
   constexpr int KC = 16, ROWS = 4 * TN, SH = ROWS + 2, SW = 18, PS = 20;
   constexpr int NXV = SH * SW * 4, NXT = (NXV + 255) / 256;  // input 16-B vectors per chunk
   constexpr int NAV = TM * 9 * 64, NAT = (NAV + 255) / 256;  // weight 16-B vectors per chunk
-  // the fused head re-lays each wave's [16 px][16 TM ch] rows out through Xs (row pitch 16 TM + 4)
-  constexpr int XS_TILE = SH * SW * PS, XS_HEAD = HEAD ? 4 * 16 * (TM * 16 + 4) : 0;
+  // the fused head's epilogue reuses Xs (re-layout and output staging regions)
+  constexpr int XS_TILE = SH * SW * PS, XS_HEAD = HEAD ? head_lds_elems<float, float, TM>() : 0;
   __shared__ __attribute__((aligned(16))) float Xs[XS_TILE > XS_HEAD ? XS_TILE : XS_HEAD];
   __shared__ __attribute__((aligned(16))) float As[NAV * 4];
 
