@@ -17,7 +17,9 @@ __device__ inline float logit_value(uint16_t v) { return bf2f(v); }
 // the demodulation map d = exp(clamp(z, -8, 8)) (the same as aps_remodulate)
 __device__ inline float demod_scale(float z) { return expf(fminf(fmaxf(z, -8.f), 8.f)); }
 
-template <int KD, int KU, int KT, bool HU, bool HT, typename LT>
+// DM: learned demodulation at this level (a.hist set); its kernels are separate instances so
+// that the registers holding the map do not lower the occupancy of the others.
+template <int KD, int KU, int KT, bool HU, bool HT, typename LT, bool DM>
 __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   using G = Geo<KD, KU, KT, HU, HT>;
   constexpr int NK = G::NK;
@@ -34,10 +36,31 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   const bool in = x < W && y < H;
 
   float z[NKP];
+  // with learned demodulation, the map's three channels (and the four latents) of the same
+  // logit row, loaded here so that the epilogue issues no load after its first store; bf16
+  // values are kept packed two to a register until the end
+  constexpr int DW = sizeof(LT) == 2 ? 2 : 4;  // registers for the map and for the latents
+  uint32_t dz[DW] = {}, lz[DW] = {};
   if (in) {
     const LT* lp = static_cast<const LT*>(a.logits) + (((size_t)n * H + y) * W + x) * a.kstride;
     LogitVec<LT>::template load<NKP>(lp, z);
+    if constexpr (DM) {
+      auto grab = [&](int off, int cnt, uint32_t* r) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (c >= cnt) break;
+          if constexpr (sizeof(LT) == 2) r[c / 2] |= (uint32_t)lp[off + c] << (16 * (c & 1));
+          else r[c] = __builtin_bit_cast(uint32_t, lp[off + c]);
+        }
+      };
+      grab(a.remod, 3, dz);
+      if (a.lat) grab(a.lat_off, 4, lz);
+    }
   }
+  auto unpack = [](const uint32_t* r, int c) {
+    if constexpr (sizeof(LT) == 2) return bf2f((uint16_t)(r[c / 2] >> (16 * (c & 1))));
+    else return __builtin_bit_cast(float, r[c]);
+  };
   stage_tiles<G>(a, Ls, Cs, Ts, x0, y0, n, HU, HT);
   __syncthreads();
   if (!in) return;
@@ -67,15 +90,12 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
     o.y += p.y;
     o.z += p.z;
   }
-  if (a.hist) {  // remodulation, reading the map from the logit row loaded above
-    const LT* row = static_cast<const LT*>(a.logits) + pix * a.kstride;
+  if constexpr (DM) {  // remodulation with the map loaded at the start
     a.hist[pix] = o;
-    o.x *= demod_scale(logit_value(row[a.remod]));
-    o.y *= demod_scale(logit_value(row[a.remod + 1]));
-    o.z *= demod_scale(logit_value(row[a.remod + 2]));
-    if (a.lat)
-      a.lat[pix] = make_float4(logit_value(row[a.lat_off]), logit_value(row[a.lat_off + 1]),
-                               logit_value(row[a.lat_off + 2]), logit_value(row[a.lat_off + 3]));
+    o.x *= demod_scale(unpack(dz, 0));
+    o.y *= demod_scale(unpack(dz, 1));
+    o.z *= demod_scale(unpack(dz, 2));
+    if (a.lat) a.lat[pix] = make_float4(unpack(lz, 0), unpack(lz, 1), unpack(lz, 2), unpack(lz, 3));
   }
   *dst = o;
 }
@@ -83,10 +103,17 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
 template <int KD, int KU, int KT, typename LT>
 int launch_level_t(const LevelArgs& a, bool hu, bool ht, int N, hipStream_t st) {
   dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, N);
-  if (hu && ht) k_level<KD, KU, KT, true, true, LT><<<grid, 256, 0, st>>>(a);
-  else if (hu) k_level<KD, KU, KT, true, false, LT><<<grid, 256, 0, st>>>(a);
-  else if (ht) k_level<KD, KU, KT, false, true, LT><<<grid, 256, 0, st>>>(a);
-  else k_level<KD, KU, KT, false, false, LT><<<grid, 256, 0, st>>>(a);
+  if (a.hist) {
+    if (hu && ht) k_level<KD, KU, KT, true, true, LT, true><<<grid, 256, 0, st>>>(a);
+    else if (hu) k_level<KD, KU, KT, true, false, LT, true><<<grid, 256, 0, st>>>(a);
+    else if (ht) k_level<KD, KU, KT, false, true, LT, true><<<grid, 256, 0, st>>>(a);
+    else k_level<KD, KU, KT, false, false, LT, true><<<grid, 256, 0, st>>>(a);
+  } else {
+    if (hu && ht) k_level<KD, KU, KT, true, true, LT, false><<<grid, 256, 0, st>>>(a);
+    else if (hu) k_level<KD, KU, KT, true, false, LT, false><<<grid, 256, 0, st>>>(a);
+    else if (ht) k_level<KD, KU, KT, false, true, LT, false><<<grid, 256, 0, st>>>(a);
+    else k_level<KD, KU, KT, false, false, LT, false><<<grid, 256, 0, st>>>(a);
+  }
   APS_LAUNCH_CHECK();
   return APS_OK;
 }
