@@ -161,12 +161,13 @@ def bench_config(name, steps, warmup, dev, seed=2602):
             feat = ops.assemble_features("kernel", aux, Ls[0], s, prev, mv, cfg.kernel_cin, cfg.net_dtype,
                                          lat=r._lat(prev))
         mark(4)
+        zmap = None
         if r.knet is not None:
-            z = ops.kernel_predict(r.knet, feat, cfg.head_channels(), cfg.logit_dtype)
+            z, zmap = r.kernel_logits(feat)
         else:
             z = r.logits(aux, Ls[0], s)
         mark(5)
-        out = r.filter(Ls, z, prev, mv)
+        out = r.filter(Ls, z, prev, mv, zmap=zmap)
         mark(6)
         return out
 

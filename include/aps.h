@@ -117,6 +117,17 @@ int aps_conv2d_fwd_head(const void* x, const void* x2, int N, int H, int W, int 
                         int mode, const void* packed_w, const float* bias, int Cout, int relu,
                         const void* packed_head, const float* head_bias, int K, int dtype,
                         void* y, int ldy, void* logits, int kstride, void* stream);
+/* The same with a side output for learned demodulation (Sec. 6.2): side [N,H,W,4] (dtype)
+ * receives logit channels [side_offset, side_offset + 3) of every pixel and a 0, the
+ * compact demodulation map that aps_demodulate reads with z_stride 4 and z_offset 0 instead
+ * of whole logit rows.  side NULL: as aps_conv2d_fwd_head.  Requires side_offset + 3 <= K;
+ * APS_ERR_UNSUPPORTED unless kstride <= 64, kstride * element size is a multiple of 16 bytes,
+ * logits is 16-byte aligned and side aligned to one pixel (8 or 16 bytes). */
+int aps_conv2d_fwd_head_ex(const void* x, const void* x2, int N, int H, int W, int Cx, int C2,
+                           int mode, const void* packed_w, const float* bias, int Cout, int relu,
+                           const void* packed_head, const float* head_bias, int K, int dtype,
+                           void* y, int ldy, void* logits, int kstride, void* side,
+                           int side_offset, void* stream);
 
 /* ---------------------------------------------------------------- a1 + a2: density
  * Sec. 3 (Overview): the sampler predicts one channel z; s = f*B + (1-f)*B*Npx*softmax(z)
@@ -243,6 +254,15 @@ size_t aps_kernel_predict_workspace_size(const aps_net* net, int N, int H, int W
 int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W, int C,
                        int n_heads, void* const* logits, int logit_dtype, const int* kstride,
                        void* ws, size_t ws_bytes, void* stream);
+/* The same with the compact demodulation map of head 0 (Sec. 6.2): side0 [N,H,W,4] in the
+ * logit dtype receives logits[0] channels [side0_offset, side0_offset + 3) and a 0 (see
+ * aps_conv2d_fwd_head_ex).  It is written by the fused level-0 head, so it needs logit_dtype
+ * equal to the net's dtype; APS_ERR_UNSUPPORTED when that head cannot be fused or the
+ * conditions of aps_conv2d_fwd_head_ex do not hold.  side0 NULL: as aps_kernel_predict. */
+int aps_kernel_predict_ex(const aps_net* net, const void* feat, int N, int H, int W, int C,
+                          int n_heads, void* const* logits, int logit_dtype, const int* kstride,
+                          void* side0, int side0_offset, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* ---------------------------------------------------------------- a6-a9: reconstruction
  * Logits of level l: [N, H_l, W_l, kstride_l] (float32 or bf16; kstride_l a multiple of 4

@@ -36,6 +36,7 @@ SIGNATURES = {
     "aps_conv_pack_weights": (I, [P, I, I, I, I, P, P]),
     "aps_conv2d_fwd": (I, [P, P, I, I, I, I, I, I, P, P, I, I, I, I, P, I, I, P]),
     "aps_conv2d_fwd_head": (I, [P, P, I, I, I, I, I, I, P, P, I, I, P, P, I, I, P, I, P, I, P]),
+    "aps_conv2d_fwd_head_ex": (I, [P, P, I, I, I, I, I, I, P, P, I, I, P, P, I, I, P, I, P, I, P, I, P]),
     "aps_conv2d_fwd_pool": (I, [P, P, I, I, I, I, I, I, P, P, I, I, I, P, P, P]),
     "aps_normalize_workspace_size": (SZ, [I, I, I]),
     "aps_normalize_density": (I, [P, I, I, I, F, F, P, P, SZ, P, P]),
@@ -57,6 +58,7 @@ SIGNATURES = {
     "aps_assemble_features_ex": (I, [I, P, P, P, P, P, P, I, I, I, I, I, P, P]),
     "aps_kernel_predict_workspace_size": (SZ, [C.POINTER(NetDesc), I, I, I]),
     "aps_kernel_predict": (I, [C.POINTER(NetDesc), P, I, I, I, I, I, P, I, P, P, SZ, P]),
+    "aps_kernel_predict_ex": (I, [C.POINTER(NetDesc), P, I, I, I, I, I, P, I, P, P, I, P, SZ, P]),
     "aps_denoise_pyramid_workspace_size": (SZ, [I, I, I, I]),
     "aps_denoise_pyramid": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, P, P, SZ, P]),
     "aps_denoise_pyramid_ex": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, I, I, P, P, P, P, SZ, P]),
@@ -107,10 +109,12 @@ def load():
 
 
 class ApsError(RuntimeError):
-    pass
+    def __init__(self, msg: str, status: int = -1):
+        super().__init__(msg)
+        self.status = status
 
 
 def check(status: int, what: str = ""):
     if status != 0:
         msg = load().aps_status_string(status).decode()
-        raise ApsError(f"{what}: aps status {status} ({msg})")
+        raise ApsError(f"{what}: aps status {status} ({msg})", status)

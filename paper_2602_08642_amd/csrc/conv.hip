@@ -33,6 +33,10 @@ struct ConvArgs {
   int hK;
   void* hy;
   int hldy, store_main;
+  // optional side output of three head channels [hside_off, hside_off + 3) as [N,H,W,4] (the
+  // fourth entry 0), written from the staged logit rows (conv_epilogue)
+  void* hside;
+  int hside_off;
   // optional 2x2 average pool of the (bf16-rounded) output, [N, H/2, W/2, Cout] (k_conv_lds)
   void* pool;
   int ntiles, nco;  // pixel tiles per image, output-channel blocks (block order: xcd_tile)
@@ -334,6 +338,14 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
           uint4* dst = reinterpret_cast<uint4*>(hy + (((size_t)n * a.H + row) * a.W + tx0) * a.hldy);
           const uint4* src = reinterpret_cast<const uint4*>(Os);
           for (int v = lane; v < nvec; v += 64) dst[v] = src[v];
+          if (a.hside && lane < npx) {
+            const TO* op = Os + lane * a.hldy + a.hside_off;
+            TO* sp = static_cast<TO*>(a.hside) + (((size_t)n * a.H + row) * a.W + tx0 + lane) * 4;
+            if constexpr (sizeof(TO) == 2)
+              *reinterpret_cast<u16x4*>(sp) = u16x4{op[0], op[1], op[2], (uint16_t)0};
+            else
+              *reinterpret_cast<f32x4*>(sp) = f32x4{op[0], op[1], op[2], 0.f};
+          }
         }
       } else {
 #pragma unroll
@@ -1798,7 +1810,25 @@ int aps_conv2d_fwd_head(const void* x, const void* x2, int N, int H, int W, int 
                         int mode, const void* packed_w, const float* bias, int Cout, int relu,
                         const void* packed_head, const float* head_bias, int K, int dtype,
                         void* y, int ldy, void* logits, int kstride, void* stream) {
+  return aps_conv2d_fwd_head_ex(x, x2, N, H, W, Cx, C2, mode, packed_w, bias, Cout, relu,
+                                packed_head, head_bias, K, dtype, y, ldy, logits, kstride, nullptr,
+                                -1, stream);
+}
+
+int aps_conv2d_fwd_head_ex(const void* x, const void* x2, int N, int H, int W, int Cx, int C2,
+                           int mode, const void* packed_w, const float* bias, int Cout, int relu,
+                           const void* packed_head, const float* head_bias, int K, int dtype,
+                           void* y, int ldy, void* logits, int kstride, void* side,
+                           int side_offset, void* stream) {
   if (N < 0 || H < 0 || W < 0 || Cx <= 0 || C2 < 0 || K <= 0 || kstride < K) return APS_ERR_SHAPE;
+  if (side) {
+    if (side_offset < 0 || side_offset + 3 > K) return APS_ERR_SHAPE;
+    // the side output is written from the staged logit rows (conv_epilogue)
+    const size_t es = dtype == APS_BF16 ? 2 : 4;
+    if (kstride > 64 || (kstride * es) % 16 || (reinterpret_cast<uintptr_t>(logits) & 15) ||
+        (reinterpret_cast<uintptr_t>(side) & (4 * es - 1)))
+      return APS_ERR_UNSUPPORTED;
+  }
   if (Cout != 32 && Cout != 64) return APS_ERR_UNSUPPORTED;
   if (K > 64 || Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2) != 4) return APS_ERR_UNSUPPORTED;
   if (y && ldy < Cout) return APS_ERR_SHAPE;
@@ -1834,6 +1864,8 @@ int aps_conv2d_fwd_head(const void* x, const void* x2, int N, int H, int W, int 
   a.hy = logits;
   a.hldy = kstride;
   a.store_main = y != nullptr;
+  a.hside = side;
+  a.hside_off = side_offset;
   hipStream_t st = as_stream(stream);
   if (dtype == APS_F32 && !fp32_offsets_fit(mode, N, H, W, Cx, C2)) return APS_ERR_UNSUPPORTED;
   if (dtype == APS_F32) {

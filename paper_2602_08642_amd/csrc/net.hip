@@ -194,6 +194,14 @@ size_t aps_kernel_predict_workspace_size(const aps_net* net, int N, int H, int W
 int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W, int C,
                        int n_heads, void* const* logits, int logit_dtype, const int* kstride,
                        void* ws, size_t ws_bytes, void* stream) {
+  return aps_kernel_predict_ex(net, feat, N, H, W, C, n_heads, logits, logit_dtype, kstride,
+                               nullptr, -1, ws, ws_bytes, stream);
+}
+
+int aps_kernel_predict_ex(const aps_net* net, const void* feat, int N, int H, int W, int C,
+                          int n_heads, void* const* logits, int logit_dtype, const int* kstride,
+                          void* side0, int side0_offset, void* ws, size_t ws_bytes,
+                          void* stream) {
   if (!net) return APS_ERR_NULL;
   if (n_heads < 1 || n_heads > 5 || net->n_layers != kUnetConvs + n_heads) return APS_ERR_SHAPE;
   const int div = n_heads > 4 ? 16 : 8;
@@ -284,13 +292,15 @@ int aps_kernel_predict(const aps_net* net, const void* feat, int N, int H, int W
     const aps_conv_layer& Hd = L[kUnetConvs];
     if (A.w && A.b && Hd.w && Hd.b && A.cin == L[12].cout && Hd.cin == A.cout && Hd.ksize == 1 &&
         A.ksize == 3) {
-      const int r = aps_conv2d_fwd_head(t, nullptr, N, H, W, L[12].cout, 0, APS_CONV_DIRECT, A.w,
-                                        A.b, A.cout, A.relu, Hd.w, Hd.b, Hd.cout, dt, nullptr, 0,
-                                        logits[0], kstride[0], stream);
+      const int r = aps_conv2d_fwd_head_ex(t, nullptr, N, H, W, L[12].cout, 0, APS_CONV_DIRECT,
+                                           A.w, A.b, A.cout, A.relu, Hd.w, Hd.b, Hd.cout, dt,
+                                           nullptr, 0, logits[0], kstride[0], side0, side0_offset,
+                                           stream);
       if (r == APS_OK) fused0 = true;
       else if (r != APS_ERR_UNSUPPORTED) return r;
     }
   }
+  if (side0 && !fused0) return APS_ERR_UNSUPPORTED;  // the side output comes from the fused head
   if (!fused0)
     APS_TRY(conv(L[13], t, nullptr, N, H, W, L[12].cout, 0, APS_CONV_DIRECT, dt, d0, c0, dt, stream));
   // remaining 1x1 heads (head 4 reads the bottleneck through the 2x2-pool input transform)

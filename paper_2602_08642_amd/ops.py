@@ -339,7 +339,10 @@ def round_kstride(K: int, dtype) -> int:
     return (K + v - 1) // v * v
 
 
-def kernel_predict(net: Net, feat, head_channels, logit_dtype=_F32):
+def kernel_predict(net: Net, feat, head_channels, logit_dtype=_F32, side_offset=None):
+    """-> logits (list per level); with side_offset, (logits, side): side [N,H,W,4] holds
+    logits[0][..., side_offset:side_offset+3] and a 0 (the compact demodulation map, written
+    by the fused level-0 head)."""
     _need(feat, "feat", net.dtype)
     N, H, W, Cf = feat.shape
     n = len(head_channels)
@@ -351,9 +354,15 @@ def kernel_predict(net: Net, feat, head_channels, logit_dtype=_F32):
     ws = WS.get(nb, feat.device)
     arr = (C.c_void_p * 5)(*[t.data_ptr() for t in logits])
     karr = (C.c_int * 5)(*ks)
-    L.check(lib.aps_kernel_predict(C.byref(net.desc), _p(feat), N, H, W, Cf, n, arr,
-                                   _dt(logit_dtype), karr, _p(ws), nb, _stream()), "kernel_predict")
-    return logits
+    if side_offset is None:
+        L.check(lib.aps_kernel_predict(C.byref(net.desc), _p(feat), N, H, W, Cf, n, arr,
+                                       _dt(logit_dtype), karr, _p(ws), nb, _stream()), "kernel_predict")
+        return logits
+    side = torch.empty((N, H, W, 4), dtype=logit_dtype, device=feat.device)
+    L.check(lib.aps_kernel_predict_ex(C.byref(net.desc), _p(feat), N, H, W, Cf, n, arr,
+                                      _dt(logit_dtype), karr, _p(side), int(side_offset), _p(ws), nb,
+                                      _stream()), "kernel_predict")
+    return logits, side
 
 
 # ------------------------------------------------------------------ reconstruction (a6-a9)

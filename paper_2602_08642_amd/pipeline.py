@@ -10,7 +10,7 @@ import dataclasses
 
 import torch
 
-from . import ops
+from . import _lib, ops
 
 F32, BF16 = torch.float32, torch.bfloat16
 
@@ -118,6 +118,7 @@ class FrameRenderer:
         self._const_logits = None
         self.history = None
         self.latent = None      # the latest frame's latents [N,H,W,4], read by the next frame
+        self.zmap = None        # the latest frame's compact demodulation map (kernel_logits)
         self.u_tex = None
         if cfg.u_noise == "blue":   # a 64x64 void-and-cluster threshold texture (Sec. 6.3)
             import procgen
@@ -167,7 +168,22 @@ class FrameRenderer:
                 ld = ops.round_kstride(l["cout"], cfg.logit_dtype) if last else None
                 h = ops.conv2d(h, sp, pk, b, out_dtype=cfg.logit_dtype if last else None, ldy=ld)
             return [h]
-        return ops.kernel_predict(self.knet, feat, cfg.head_channels(), cfg.logit_dtype)
+        z, self.zmap = self.kernel_logits(feat)
+        return z
+
+    def kernel_logits(self, feat):
+        """U-Net logits, and with learned demodulation the compact [N,H,W,4] map that the fused
+        level-0 head writes beside them (None where that head cannot write it: the map is then
+        read from the logit rows)."""
+        cfg = self.cfg
+        if cfg.demod and cfg.logit_dtype == cfg.net_dtype:
+            try:
+                return ops.kernel_predict(self.knet, feat, cfg.head_channels(), cfg.logit_dtype,
+                                          side_offset=cfg.filter_channels()[0])
+            except _lib.ApsError as e:
+                if e.status != _lib.APS_ERR_UNSUPPORTED:
+                    raise
+        return ops.kernel_predict(self.knet, feat, cfg.head_channels(), cfg.logit_dtype), None
 
     def reconstruct(self, aux, s, req, samples, seed: int, frame: int, prev=None, mv=None,
                     mode="hard", lam=10.0, history=None):
@@ -176,9 +192,10 @@ class FrameRenderer:
                                  lam, seed, frame, u_tex=self.u_tex)
         use_prev = prev if cfg.temporal else None
         use_mv = mv if cfg.temporal else None
+        self.zmap = None
         z = self.logits(aux, Ls[0], s, use_prev, use_mv)
         hist = (history if history is not None else prev) if cfg.temporal else None
-        out, self.history = self.filter(Ls, z, hist, use_mv, want_history=True)
+        out, self.history = self.filter(Ls, z, hist, use_mv, want_history=True, zmap=self.zmap)
         return out, Ls, z
 
     def _lat(self, prev):
@@ -187,15 +204,19 @@ class FrameRenderer:
             return None
         return self.latent
 
-    def filter(self, Ls, z, history=None, mv=None, want_history=False):
+    def filter(self, Ls, z, history=None, mv=None, want_history=False, zmap=None):
         """Gathering pyramid.  With learned demodulation the pyramid of L0 / d is filtered and the
         result multiplied by d (d from the level-0 head channels after the kernel logits); the
         filter then works in demodulated space throughout, so its temporal input (history) is the
-        previous frame's demodulated reconstruction, which want_history also returns."""
+        previous frame's demodulated reconstruction, which want_history also returns.  zmap: the
+        compact copy of those three channels (kernel_logits), else they are read from z[0]."""
         cfg = self.cfg
         if cfg.demod:
             k0 = cfg.filter_channels()[0]
-            Ld = ops.demodulate(Ls[0], z[0], k0, cfg.levels)
+            if zmap is not None:
+                Ld = ops.demodulate(Ls[0], zmap, 0, cfg.levels)
+            else:
+                Ld = ops.demodulate(Ls[0], z[0], k0, cfg.levels)
             out_d = torch.empty_like(Ls[0])
             lat = None
             if cfg.latents:   # copied from the level-0 logit rows the map is read from

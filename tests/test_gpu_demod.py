@@ -210,3 +210,45 @@ def test_fused_remodulation_equals_separate_passes(ops):
     assert torch.equal(fused, sep)
     assert torch.equal(out_d, plain)
     assert torch.equal(lat, zs[0][..., 57:61].float())
+
+
+@pytest.mark.parametrize("dtype,heads,k0", [(torch.bfloat16, [61, 29, 29], 54),
+                                            (torch.float32, [50, 34, 25], 43),
+                                            (torch.bfloat16, [46, 34, 25], 43)])
+def test_kernel_predict_writes_the_compact_map(ops, dtype, heads, k0):
+    """The fused level-0 head's side output: the three map channels of every pixel bit for bit
+    as in logits[0], a zero after them, the logits unchanged; the demodulated pyramid built from
+    the compact map equals the one read from the logit rows.  Width 40 leaves a partial pixel
+    tile at the right edge."""
+    import procgen
+    spec = procgen.unet_spec(24, heads)
+    net = ops.Net(spec, procgen.init_weights(spec, 41), dtype, DEV)
+    x = torch.randn(2, 32, 40, 24, generator=torch.Generator().manual_seed(8)).to(DEV).to(dtype)
+    plain = ops.kernel_predict(net, x, heads, dtype)
+    logits, side = ops.kernel_predict(net, x, heads, dtype, side_offset=k0)
+    for a, b, K in zip(plain, logits, heads):   # channels past K are row padding
+        assert torch.equal(a[..., :K], b[..., :K])
+    assert side.shape == (2, 32, 40, 4) and side.dtype == dtype
+    assert torch.equal(side[..., :3], logits[0][..., k0:k0 + 3])
+    assert torch.equal(side[..., 3], torch.zeros_like(side[..., 3]))
+    L0 = torch.randn(2, 32, 40, 4, generator=torch.Generator().manual_seed(9)).to(DEV)
+    for a, b in zip(ops.demodulate(L0, side, 0, 3), ops.demodulate(L0, logits[0], k0, 3)):
+        assert torch.equal(a, b)
+
+
+def test_compact_map_argument_checks(ops):
+    """The map must lie inside the head's channels; it is written by the fused head only, so a
+    logit dtype other than the net's is refused as unsupported (the caller then reads the map
+    from the logit rows)."""
+    import procgen
+    from paper_2602_08642_amd import _lib
+    heads = [61, 29, 29]
+    spec = procgen.unet_spec(24, heads)
+    net = ops.Net(spec, procgen.init_weights(spec, 42), torch.bfloat16, DEV)
+    x = torch.zeros(1, 16, 16, 24, dtype=torch.bfloat16, device=DEV)
+    with pytest.raises(_lib.ApsError) as e:
+        ops.kernel_predict(net, x, heads, torch.bfloat16, side_offset=59)
+    assert e.value.status == _lib.APS_ERR_SHAPE
+    with pytest.raises(_lib.ApsError) as e:
+        ops.kernel_predict(net, x, heads, torch.float32, side_offset=54)
+    assert e.value.status == _lib.APS_ERR_UNSUPPORTED
