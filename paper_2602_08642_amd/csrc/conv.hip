@@ -1240,8 +1240,113 @@ void launch_conv_head(const ConvArgs& a, hipStream_t st) {
   else k_conv<T, T, 3, TM, 2, 4, true><<<grid, 256, 0, st>>>(b);
 }
 
+// ---- bf16 1x1 convolution for the logit heads -------------------------------------------------
+// One wave per 16 consecutive output pixels and all MT m-tiles (Cout <= 16 MT); no LDS and no
+// barriers: each lane loads its B fragments straight from global memory (pixel lane % 16,
+// channels 32 c + 8 (lane / 16) + [0, 8) of chunk c, zero past Cin), the A fragments are the
+// packed weights (L2-resident).  The heads at the coarse levels have few pixels, so the tiled
+// kernel's block-wide chunk loop (stage, barrier, MFMAs, barrier) left most of the chip idle
+// and serialised one memory round trip per chunk.  The MFMA sequence and the POOL2 transform
+// (2x2 mean of the bf16 inputs in fp32, rounded to bf16) are those of k_conv, so the results are
+// the same bit for bit.
+template <typename TO, int MT, bool POOL>
+__global__ __launch_bounds__(256) void k_conv1x1(ConvArgs a) {
+  constexpr int MAXC = 8;  // Cin <= 256
+  const int lane = threadIdx.x & 63;
+  const size_t npix = (size_t)a.N * a.H * a.W;
+  const size_t p0 = ((size_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (p0 >= npix) return;  // whole waves
+  const size_t pix = p0 + (lane & 15);
+  const bool inpx = pix < npix;
+  const size_t pc = inpx ? pix : p0;  // a valid pixel for the loads of lanes past the end
+  const int g8 = 8 * (lane >> 4);
+  const uint16_t* x = static_cast<const uint16_t*>(a.x);
+  const uint16_t* wp = static_cast<const uint16_t*>(a.wp);
+  size_t xo;
+  if constexpr (POOL) {
+    const size_t hw = (size_t)a.H * a.W, n = pc / hw, r = pc - n * hw;
+    const size_t yy = r / a.W, xx = r - yy * a.W;
+    xo = ((n * 2 * a.H + 2 * yy) * (2 * (size_t)a.W) + 2 * xx) * a.Cx;
+  } else {
+    xo = pc * a.Cx;
+  }
+  Frag<uint16_t> b[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) {
+    if (c >= a.nchunk) break;
+    const int ci = c * kChunk + g8;
+    const bool ok = inpx && ci < a.Cx;
+    const size_t o = xo + (ok ? ci : 0);
+    if constexpr (POOL) {
+      const size_t rs = 2 * (size_t)a.W * a.Cx;
+      const V8f q0 = load8(x + o), q1 = load8(x + o + a.Cx), q2 = load8(x + o + rs),
+                q3 = load8(x + o + rs + a.Cx);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        b[c].v[e] = ok ? f2bf(((q0.v[e] + q1.v[e]) + (q2.v[e] + q3.v[e])) * 0.25f) : (uint16_t)0;
+    } else {
+      const u16x8 v = *reinterpret_cast<const u16x8*>(x + o);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[c].v[e] = ok ? v[e] : (uint16_t)0;
+    }
+  }
+  f32x4 acc[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) {
+    if (c >= a.nchunk) break;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      Frag<uint16_t> w;
+      frag_load(w, wp + (((size_t)m * a.nchunk + c) * 64 + lane) * 8);
+      acc[m] = mma(w, b[c], acc[m]);
+    }
+  }
+  if (!inpx) return;
+  TO* py = static_cast<TO*>(a.y) + pix * a.ldy;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int co0 = m * 16 + 4 * (lane >> 4);
+    if (co0 >= a.Cout) continue;
+    float v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // no bias for the input-gradient convolutions (aps_conv2d_bwd_data passes none)
+      const float t = acc[m][q] + (a.bias && co0 + q < a.Cout ? a.bias[co0 + q] : 0.f);
+      v[q] = a.relu ? fmaxf(t, 0.f) : t;
+    }
+    store_out<TO>(py, a.ldy, co0, a.Cout, v);
+  }
+}
+
+// false: not covered (the caller uses k_conv)
+template <typename TO>
+bool launch_conv1x1(const ConvArgs& a, hipStream_t st) {
+  if (a.C2 != 0 || a.Cx % 8 || a.nchunk > 8 || a.Cout > 64) return false;
+  if (a.mode != APS_CONV_DIRECT && a.mode != APS_CONV_POOL2) return false;
+  const size_t npix = (size_t)a.N * a.H * a.W;
+  const size_t blocks = (npix + 63) / 64;
+  if (blocks > 0x7fffffff) return false;
+  const dim3 grid((unsigned)blocks);
+  const int mt = (a.Cout + 15) / 16;
+  const bool pool = a.mode == APS_CONV_POOL2;
+#define APS_C1X1(MT)                                                          \
+  if (pool) k_conv1x1<TO, MT, true><<<grid, 256, 0, st>>>(a);                 \
+  else k_conv1x1<TO, MT, false><<<grid, 256, 0, st>>>(a);
+  if (mt == 1) { APS_C1X1(1) }
+  else if (mt == 2) { APS_C1X1(2) }
+  else if (mt == 3) { APS_C1X1(3) }
+  else { APS_C1X1(4) }
+#undef APS_C1X1
+  return true;
+}
+
 template <typename T, typename TO, int KS, int CG>
 void dispatch_tiles(const ConvArgs& a, hipStream_t st) {
+  if constexpr (sizeof(T) == 2 && KS == 1) {
+    if (launch_conv1x1<TO>(a, st)) return;
+  }
   if constexpr (sizeof(T) == 2 && sizeof(TO) == 2 && KS == 3 && CG == 4) {
     if (launch_conv_lds<false>(a, st)) return;
   }
