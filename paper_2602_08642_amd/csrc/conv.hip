@@ -1240,16 +1240,16 @@ void launch_conv_head(const ConvArgs& a, hipStream_t st) {
   else k_conv<T, T, 3, TM, 2, 4, true><<<grid, 256, 0, st>>>(b);
 }
 
-// ---- bf16 1x1 convolution for the logit heads -------------------------------------------------
+// ---- 1x1 convolution for the logit heads -------------------------------------------------------
 // One wave per 16 consecutive output pixels and all MT m-tiles (Cout <= 16 MT); no LDS and no
 // barriers: each lane loads its B fragments straight from global memory (pixel lane % 16,
 // channels 32 c + 8 (lane / 16) + [0, 8) of chunk c, zero past Cin), the A fragments are the
 // packed weights (L2-resident).  The heads at the coarse levels have few pixels, so the tiled
 // kernel's block-wide chunk loop (stage, barrier, MFMAs, barrier) left most of the chip idle
 // and serialised one memory round trip per chunk.  The MFMA sequence and the POOL2 transform
-// (2x2 mean of the bf16 inputs in fp32, rounded to bf16) are those of k_conv, so the results are
-// the same bit for bit.
-template <typename TO, int MT, bool POOL>
+// (2x2 mean of the inputs in fp32, rounded to T) are those of k_conv, so the results are the same
+// bit for bit.
+template <typename T, typename TO, int MT, bool POOL>
 __global__ __launch_bounds__(256) void k_conv1x1(ConvArgs a) {
   constexpr int MAXC = 8;  // Cin <= 256
   const int lane = threadIdx.x & 63;
@@ -1260,8 +1260,8 @@ __global__ __launch_bounds__(256) void k_conv1x1(ConvArgs a) {
   const bool inpx = pix < npix;
   const size_t pc = inpx ? pix : p0;  // a valid pixel for the loads of lanes past the end
   const int g8 = 8 * (lane >> 4);
-  const uint16_t* x = static_cast<const uint16_t*>(a.x);
-  const uint16_t* wp = static_cast<const uint16_t*>(a.wp);
+  const T* x = static_cast<const T*>(a.x);
+  const T* wp = static_cast<const T*>(a.wp);
   size_t xo;
   if constexpr (POOL) {
     const size_t hw = (size_t)a.H * a.W, n = pc / hw, r = pc - n * hw;
@@ -1270,7 +1270,7 @@ __global__ __launch_bounds__(256) void k_conv1x1(ConvArgs a) {
   } else {
     xo = pc * a.Cx;
   }
-  Frag<uint16_t> b[MAXC];
+  Frag<T> b[MAXC];
 #pragma unroll
   for (int c = 0; c < MAXC; ++c) {
     if (c >= a.nchunk) break;
@@ -1282,12 +1282,19 @@ __global__ __launch_bounds__(256) void k_conv1x1(ConvArgs a) {
       const V8f q0 = load8(x + o), q1 = load8(x + o + a.Cx), q2 = load8(x + o + rs),
                 q3 = load8(x + o + rs + a.Cx);
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        b[c].v[e] = ok ? f2bf(((q0.v[e] + q1.v[e]) + (q2.v[e] + q3.v[e])) * 0.25f) : (uint16_t)0;
-    } else {
+      for (int e = 0; e < 8; ++e) {
+        const float r = ((q0.v[e] + q1.v[e]) + (q2.v[e] + q3.v[e])) * 0.25f;
+        if constexpr (sizeof(T) == 2) b[c].v[e] = ok ? f2bf(r) : (uint16_t)0;
+        else b[c].v[e] = ok ? r : 0.f;
+      }
+    } else if constexpr (sizeof(T) == 2) {
       const u16x8 v = *reinterpret_cast<const u16x8*>(x + o);
 #pragma unroll
       for (int e = 0; e < 8; ++e) b[c].v[e] = ok ? v[e] : (uint16_t)0;
+    } else {
+      const V8f v = load8(x + o);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[c].v[e] = ok ? v.v[e] : 0.f;
     }
   }
   f32x4 acc[MT];
@@ -1298,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_conv1x1(ConvArgs a) {
     if (c >= a.nchunk) break;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      Frag<uint16_t> w;
+      Frag<T> w;
       frag_load(w, wp + (((size_t)m * a.nchunk + c) * 64 + lane) * 8);
       acc[m] = mma(w, b[c], acc[m]);
     }
@@ -1321,7 +1328,7 @@ __global__ __launch_bounds__(256) void k_conv1x1(ConvArgs a) {
 }
 
 // false: not covered (the caller uses k_conv)
-template <typename TO>
+template <typename T, typename TO>
 bool launch_conv1x1(const ConvArgs& a, hipStream_t st) {
   if (a.C2 != 0 || a.Cx % 8 || a.nchunk > 8 || a.Cout > 64) return false;
   if (a.mode != APS_CONV_DIRECT && a.mode != APS_CONV_POOL2) return false;
@@ -1332,8 +1339,8 @@ bool launch_conv1x1(const ConvArgs& a, hipStream_t st) {
   const int mt = (a.Cout + 15) / 16;
   const bool pool = a.mode == APS_CONV_POOL2;
 #define APS_C1X1(MT)                                                          \
-  if (pool) k_conv1x1<TO, MT, true><<<grid, 256, 0, st>>>(a);                 \
-  else k_conv1x1<TO, MT, false><<<grid, 256, 0, st>>>(a);
+  if (pool) k_conv1x1<T, TO, MT, true><<<grid, 256, 0, st>>>(a);              \
+  else k_conv1x1<T, TO, MT, false><<<grid, 256, 0, st>>>(a);
   if (mt == 1) { APS_C1X1(1) }
   else if (mt == 2) { APS_C1X1(2) }
   else if (mt == 3) { APS_C1X1(3) }
@@ -1344,8 +1351,8 @@ bool launch_conv1x1(const ConvArgs& a, hipStream_t st) {
 
 template <typename T, typename TO, int KS, int CG>
 void dispatch_tiles(const ConvArgs& a, hipStream_t st) {
-  if constexpr (sizeof(T) == 2 && KS == 1) {
-    if (launch_conv1x1<TO>(a, st)) return;
+  if constexpr (KS == 1) {
+    if (launch_conv1x1<T, TO>(a, st)) return;
   }
   if constexpr (sizeof(T) == 2 && sizeof(TO) == 2 && KS == 3 && CG == 4) {
     if (launch_conv_lds<false>(a, st)) return;
