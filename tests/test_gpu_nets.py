@@ -172,3 +172,33 @@ def test_kernel_predict_equals_layer_chain(ops, N, H, W):
     for l, (f, K) in enumerate(zip([d0, d1, d2], heads)):
         ref = conv(f"head{l}", f, ldy=ops.round_kstride(K, torch.bfloat16))
         assert torch.equal(logits[l][..., :K], ref[..., :K]), l
+
+
+@pytest.mark.parametrize("dtype,odt,tol", [(torch.bfloat16, torch.bfloat16, 2e-2),
+                                           (torch.bfloat16, torch.float32, 1e-2),
+                                           (torch.float32, torch.float32, 1e-5)])
+@pytest.mark.parametrize("cin,cout,mode", [(32, 25, "direct"), (256, 64, "direct"), (40, 34, "direct"),
+                                           (256, 29, "pool2"), (128, 61, "pool2")])
+def test_conv1x1_matches_oracle(ops, dtype, odt, tol, cin, cout, mode):
+    """The 1x1 (logit head) convolution against the FP64 oracle: a pixel count that fills no
+    whole wave (2 x 7 x 9), input channels that end inside a 32-channel chunk (40), up to 256
+    channels, the 2x2-pool input transform, and outputs into a padded row stride."""
+    from oracle import density as odens
+    from oracle import unet as ounet
+    g = torch.Generator().manual_seed(cin * 7 + cout)
+    N, H, W = 2, 7, 9
+    xin = torch.randn(N, 2 * H if mode == "pool2" else H, 2 * W if mode == "pool2" else W, cin, generator=g)
+    w = torch.randn(cout, 1, 1, cin, generator=g) / math.sqrt(cin)
+    b = torch.randn(cout, generator=g) * 0.1
+    sp = dict(name="h", cin=cin, cout=cout, k=1, relu=False)
+    net = ops.Net([sp], {"h": (w.numpy(), b.numpy())}, dtype, DEV)
+    _, pk, bb = net.layer("h")
+    ld = ops.round_kstride(cout, odt)
+    y = ops.conv2d(xin.to(DEV).to(dtype), sp, pk, bb, mode=mode, out_dtype=odt, ldy=ld)
+    assert y.shape == (N, H, W, ld)
+    x64 = xin.to(dtype).double()
+    if mode == "pool2":   # the kernel rounds the pooled input to the storage type
+        x64 = ounet.avgpool2(x64).to(dtype).double()
+    ref = odens.conv2d_nhwc(x64, w.to(dtype).double(), b.double())
+    got = y[..., :cout].double().cpu()
+    assert float((got - ref).norm() / ref.norm()) < tol
