@@ -337,7 +337,9 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
           const int nvec = npx * a.hldy * (int)sizeof(TO) / 16;
           uint4* dst = reinterpret_cast<uint4*>(hy + (((size_t)n * a.H + row) * a.W + tx0) * a.hldy);
           const uint4* src = reinterpret_cast<const uint4*>(Os);
-          for (int v = lane; v < nvec; v += 64) dst[v] = src[v];
+          // nontemporal: the logits are read back only by the filter, after the other heads
+          for (int v = lane; v < nvec; v += 64)
+            __builtin_nontemporal_store(reinterpret_cast<const u32x4*>(src)[v], reinterpret_cast<u32x4*>(dst) + v);
           if (a.hside && lane < npx) {
             const TO* op = Os + lane * a.hldy + a.hside_off;
             TO* sp = static_cast<TO*>(a.hside) + (((size_t)n * a.H + row) * a.W + tx0 + lane) * 4;
