@@ -110,6 +110,34 @@ def compare_estimators(estimators=("relaxed", "straight_through", "gumbel", "das
     return res
 
 
+VARIANTS = {
+    "plain": {},
+    "demod": {"demod": True},
+    "demod_latents": {"demod": True, "latents": 4},
+}
+
+
+def compare_variants(variants=("plain", "demod", "demod_latents"), steps=400, batch=4, frames=8, lr=1e-3,
+                     eval_seeds=tuple(range(10000, 10008)), device="cuda", cfg_name="c4", log=print):
+    """Train the learned variant (sampler + kernels, relaxed estimator) with and without learned
+    demodulation (Sec. 6.2) and the recurrent latents (Sec. 3) under the same schedule, and
+    evaluate each on the same held-out clips (hard mask) at the configuration's budget."""
+    base = pipeline.CONFIGS[cfg_name]
+    res = {"config": cfg_name, "H": base.H, "W": base.W, "budget": base.budget, "steps": steps,
+           "batch": batch, "frames": frames, "variants": {}}
+    for name in variants:
+        cfg = dataclasses.replace(base, **VARIANTS[name])
+        t0 = time.time()
+        dnet, knet, hist = train.train(cfg, train.TrainConfig(steps=steps, batch=batch, frames=frames, lr=lr),
+                                       device, log=lambda m, v=name: log(f"[{v}] " + m))
+        ev = train.evaluate(cfg, dnet, knet, list(eval_seeds), frames, device)
+        ev["train_s"] = round(time.time() - t0, 1)
+        ev["loss_first_last10"] = [hist[0]["loss"], float(np.mean([h["loss"] for h in hist[-10:]]))]
+        res["variants"][name] = ev
+        log(f"[{name}] psnr {ev['psnr']:.3f} relmse {ev['relmse']:.4f}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=300)
@@ -121,7 +149,17 @@ def main():
     ap.add_argument("--save", default=None)
     ap.add_argument("--estimators", default=None,
                     help="comma list (relaxed,straight_through,gumbel,dasr): train and compare them")
+    ap.add_argument("--variants", default=None,
+                    help="comma list (plain,demod,demod_latents): train and compare them")
     a = ap.parse_args()
+    if a.variants:
+        res = compare_variants(tuple(a.variants.split(",")), a.steps, a.batch, a.frames, a.lr,
+                               log=lambda m: print(m, flush=True))
+        print(json.dumps(res))
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     if a.estimators:
         res = compare_estimators(tuple(a.estimators.split(",")), a.steps, a.batch, a.frames, a.lr,
                                  log=lambda m: print(m, flush=True))
