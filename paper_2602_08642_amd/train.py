@@ -218,7 +218,19 @@ def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, 
     import procgen
     dspec, kspec = density_spec(cfg), kernel_spec(cfg)
     dw = dw or procgen.init_weights(dspec, 7)
-    kw = kw or procgen.init_weights(kspec, 8)
+    if kw is None:
+        kw = procgen.init_weights(kspec, 8)
+        if cfg.demod or cfg.latents:
+            # the demodulation map and the latents start at zero (d = 1: the plain path), so
+            # training departs from the path without them instead of from a random map
+            hname = kspec[-1]["name"] if cfg.kernel_net == "cnn3" else "head0"
+            k0 = cfg.filter_channels()[0]
+            w, b = kw[hname]
+            w, b = w.copy(), b.copy()
+            w[k0:] = 0.0
+            b[k0:] = 0.0
+            kw = dict(kw)
+            kw[hname] = (w, b)
     dnet = None if tc.uniform else TrainNet(dspec, dw, cfg.net_dtype, device)
     knet = TrainNet(kspec, kw, cfg.net_dtype, device)
     nets = [knet] + ([] if dnet is None else [dnet])
