@@ -135,8 +135,19 @@ __global__ __launch_bounds__(1024) void k_mask_scan(const int32_t* __restrict__ 
   const int t = threadIdx.x;
   const int per = (nb + 1023) / 1024;
   const int b0 = t * per, b1 = min(b0 + per, nb);
+  // up to kPer sums per thread are loaded into registers together (one memory round trip
+  // instead of one per loop iteration); longer segments take the loop
+  constexpr int kPer = 32;
+  int v[kPer];
   int local = 0;
-  for (int b = b0; b < b1; ++b) local += block_sum[b];
+  if (per <= kPer) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = b0 + k < b1 ? block_sum[b0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) local += v[k];
+  } else {
+    for (int b = b0; b < b1; ++b) local += block_sum[b];
+  }
   __shared__ int wsum[16];
   const int incl = wave_iscan(local);
   if ((t & 63) == 63) wsum[t >> 6] = incl;
@@ -148,9 +159,17 @@ __global__ __launch_bounds__(1024) void k_mask_scan(const int32_t* __restrict__ 
   }
   __syncthreads();
   int run = wsum[t >> 6] + incl - local;
-  for (int b = b0; b < b1; ++b) {
-    block_off[b] = run;
-    run += block_sum[b];
+  if (per <= kPer) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (b0 + k < b1) block_off[b0 + k] = run;
+      run += v[k];
+    }
+  } else {
+    for (int b = b0; b < b1; ++b) {
+      block_off[b] = run;
+      run += block_sum[b];
+    }
   }
   if (t == 1023) *total = run;
 }
