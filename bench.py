@@ -312,8 +312,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding of a "
-                                   "frame is designed (see DESIGN.md) but not built"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; sharding a frame over "
+                                   "several GPUs is not built"}))
         sys.exit(2)
 
     import torch
