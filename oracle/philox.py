@@ -2,7 +2,7 @@
 1, 2, 3", SC'11), written from its published definition in exact integer arithmetic.
 
 The paper draws one uniform variate u_i per pixel for stochastic rounding (Sec. 4.2,
-eq. holdout) and does not fix the generator; this build keys Philox with the 64-bit
+eq. holdout) and does not fix the generator; this implementation keys Philox with the 64-bit
 scene seed and counts with (pixel, frame, stream, j).  u = (word0 >> 8) * 2^-24 lies in
 [0, 1 - 2^-24] and is exact in binary32 and binary64.
 """

@@ -6,7 +6,7 @@
 * Sec. 4.3, eqs. relaxed_holdout and h_factor: in training H_i = r_i * h * ramp with a
   clipped linear ramp of slope lambda/p and h = 2 lambda / (2 lambda - 1).  The paper
   writes the ramp as clamp(lambda/p * (u + p - 1), 0, 1), which is non-zero iff
-  u > 1 - p; this build uses the mirrored variate u -> 1 - u (equally uniform), giving
+  u > 1 - p; this implementation uses the mirrored variate u -> 1 - u (equally uniform), giving
   clamp(lambda * (p - u) / p, 0, 1), non-zero iff u < p, so the relaxed forward takes
   exactly the samples of the hard mask drawn from the same u.
 * App. A, eq. app-pyramid: level l is the mean of L_noisy over 2^l x 2^l blocks.
