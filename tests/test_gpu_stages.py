@@ -320,3 +320,21 @@ def test_conv_matches_oracle(ops, cfg, dtype):
     assert_mag_close(y[..., :Cout], ref, mag, tol, what=f"{cfg} {dtype}")
     if ldy > Cout:
         assert torch.all(y[..., Cout:] == 0)
+
+
+@pytest.mark.parametrize("shape", [(1, 2160, 3840), (2, 2160, 3840)])
+def test_mask_offsets_at_4k(ops, shape):
+    """The scan of the per-block counts at 4K: one frame (32 block sums per scan thread, the
+    register path) and two frames (64 per thread, the loop path).  pixel_offset is the exclusive
+    prefix sum of the counts, total their sum, and the compacted pixel list names each pixel as
+    often as its count, in order."""
+    g = torch.Generator(device="cuda").manual_seed(11)
+    s = (torch.rand(shape, generator=g, device="cuda") * 0.5).contiguous()
+    r = ops.sample_mask(s, seed=77, frame=3)
+    cnt = r["count"].reshape(-1).to(torch.int64)
+    incl = torch.cumsum(cnt, 0)
+    assert int(r["total"].item()) == int(incl[-1].item())
+    assert torch.equal(r["pixel_offset"].reshape(-1).to(torch.int64), incl - cnt)
+    total = int(r["total"].item())
+    want = torch.repeat_interleave(torch.arange(cnt.numel(), device="cuda"), cnt)
+    assert torch.equal(r["sample_pixel"][:total].to(torch.int64), want)
