@@ -199,6 +199,44 @@ def test_normalise_and_conv_gradients_fd():
     assert torch.autograd.gradcheck(density.conv2d_nhwc, (x, w, b), eps=1e-6, atol=1e-8)
 
 
+def _srgb_decode(I):
+    """IEC 61966-2-1 decoding (the inverse of the encoding the tonemapper ends with)."""
+    I = np.asarray(I, dtype=np.float64)
+    return np.where(I <= 0.04045, I / 12.92, ((I + 0.055) / 1.055) ** 2.4)
+
+
+def _radiance_with_logs(v):
+    """A pixel whose channels have log(L + 1e-4) = v (the tonemapper's log with its epsilon)."""
+    L = torch.zeros(1, 1, 1, 4, dtype=torch.float64)
+    L[0, 0, 0, :3] = torch.tensor(np.exp(np.asarray(v, dtype=np.float64)) - 1e-4)
+    return L
+
+
+@pytest.mark.parametrize("case", [
+    # log-RGB (1, 2, 3), mean 2; saturation 1.5 -> (0.5, 2, 3.5); exposure -2.25, contrast 0.2
+    # -> x = 0.2 (sat + k) = (-0.35, -0.05, 0.25), all on the linear part for s = 0.4, h = 0.6
+    # (toe below -0.6, shoulder from 0.4): tau = (1 + x) / 2 = (0.325, 0.475, 0.625).
+    # Reading x = alpha sat + k would give (-2.15, -1.85, -1.55) (toe); saturating about the
+    # linear mean (log 10.064 = 2.309) would move every channel.
+    ((1.0, 2.0, 3.0), dict(k=-2.25, alpha=0.2, beta=1.5, s=0.4, h=0.6), (0.325, 0.475, 0.625)),
+    # log-RGB (-1, -0.25, 0.125), saturation 1, exposure 0.25, contrast 2 -> x = (-1.5, 0, 0.75);
+    # s = h = 0.5: toe 0.25 exp((x + 0.5) / 0.5) = 0.25 e^-2, line 0.5, shoulder
+    # 1 - 0.25 exp(-(x - 0.5) / 0.5) = 1 - 0.25 e^-0.5
+    ((-1.0, -0.25, 0.125), dict(k=0.25, alpha=2.0, beta=1.0, s=0.5, h=0.5),
+     (0.033833820809153176, 0.5, 0.8483673350718416)),
+    # saturation 0 collapses every channel onto the log-RGB mean (-0.5): x = 0.5 (-0.5 + 0.3)
+    # = -0.1 on the line for s = h = 0.3 -> 0.45 in every channel
+    ((-2.0, 0.0, 0.5), dict(k=0.3, alpha=0.5, beta=0.0, s=0.3, h=0.3), (0.45, 0.45, 0.45)),
+])
+def test_tonemap_hand_values(case):
+    """The composition of Sec. 5, I = sRGB(tau(alpha (sat_beta(log L) + k))) with saturation
+    about the per-pixel log-RGB mean, on hand-evaluated pixels; sRGB undone with the standard
+    decoding, so the pin does not reuse the tonemapper's own encoding."""
+    logs, prm, want_tau = case
+    I = tmo.tonemap(_radiance_with_logs(logs), prm)[0, 0, 0].numpy()
+    assert np.allclose(_srgb_decode(I), want_tau, rtol=0, atol=1e-12), (_srgb_decode(I), want_tau)
+
+
 def test_tmo_loss_gradient_fd():
     g = torch.Generator().manual_seed(9)
     L = (torch.rand(1, 4, 4, 4, generator=g, dtype=torch.float64) * 3 + 0.05).requires_grad_(True)
