@@ -10,7 +10,8 @@
  *     is launched when the code is not APS_OK.  Conditions only the device can see set
  *     bits in the optional caller-provided `dev_status` word (APS_STATUS_*), via atomic OR;
  *   - allocates nothing: scratch comes from the caller's workspace `ws` of `ws_bytes`
- *     (query with the matching *_workspace_size function).
+ *     (query with the matching *_workspace_size function); the one exception,
+ *     aps_sample_mask_noalloc, uses a fixed static device array instead.
  * An empty problem (N, H or W == 0) returns APS_OK after the size checks, before any pointer
  * check, and launches nothing (aps_sample_mask only sets *total = 0).
  * Radiance buffers are RGBA float32 (16-byte pixels, A unused and written as 0).
@@ -33,7 +34,8 @@ enum aps_status {
   APS_ERR_UNSUPPORTED = 3, /* a kernel size / dtype / level count with no compiled kernel */
   APS_ERR_WORKSPACE = 4,   /* ws missing or smaller than the query returns */
   APS_ERR_HIP = 5,         /* a HIP launch or runtime call failed */
-  APS_ERR_ARG = 6          /* a scalar argument is out of range */
+  APS_ERR_ARG = 6,         /* a scalar argument is out of range */
+  APS_ERR_TOO_LARGE = 7    /* larger than the static scratch of a no-allocation entry point */
 };
 
 enum aps_dtype { APS_F32 = 0, APS_BF16 = 1 };
@@ -187,6 +189,21 @@ int aps_sample_mask_ex(const float* s, int N, int H, int W, uint64_t seed, uint3
                        int32_t* pixel_offset, int32_t* sample_pixel, int64_t capacity,
                        int32_t* total, float* p_out, void* ws, size_t ws_bytes,
                        uint32_t* dev_status, void* stream);
+
+/* No-allocation variant of aps_sample_mask_ex, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as aps_sample_mask_ex without ws / ws_bytes: the block
+ * sums and block offsets live in a static device array of the library (1 MiB per device,
+ * kept until the process ends; its address is looked up on the stream's device at the first
+ * call there).  Limit: N*H*W <= 2^25 pixels (four 3840x2160 frames), else APS_ERR_TOO_LARGE
+ * before anything is launched.  Nothing in the array has to start at zero (every entry is
+ * written before it is read).  All calls on one device share the array: calls that overlap
+ * on one GPU (on different streams, or from different host threads) race; calls ordered on
+ * one stream do not. */
+int aps_sample_mask_noalloc(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                            const float* u_tex, int tex_size, int rounding, uint8_t* count,
+                            int32_t* pixel_offset, int32_t* sample_pixel, int64_t capacity,
+                            int32_t* total, float* p_out, uint32_t* dev_status, void* stream);
 
 /* Renderer stand-in (not part of the method): writes sample j of pixel i as
  * pool[i][j mod J] (pool float32 [N*H*W][J][4]) at samples[pixel_offset[i] + j]. */

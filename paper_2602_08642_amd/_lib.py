@@ -5,7 +5,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libaps.so")
 
-APS_OK, APS_ERR_NULL, APS_ERR_SHAPE, APS_ERR_UNSUPPORTED, APS_ERR_WORKSPACE, APS_ERR_HIP, APS_ERR_ARG = range(7)
+(APS_OK, APS_ERR_NULL, APS_ERR_SHAPE, APS_ERR_UNSUPPORTED, APS_ERR_WORKSPACE, APS_ERR_HIP, APS_ERR_ARG,
+ APS_ERR_TOO_LARGE) = range(8)
 APS_F32, APS_BF16 = 0, 1
 APS_HARD, APS_RELAXED, APS_STRAIGHT_THROUGH, APS_GUMBEL, APS_DASR = range(5)
 APS_ROUND_STOCHASTIC, APS_ROUND_HOLDOUT, APS_ROUND_DETERMINISTIC = range(3)
@@ -51,6 +52,7 @@ SIGNATURES = {
     "aps_sample_mask_workspace_size": (SZ, [I, I, I]),
     "aps_sample_mask": (I, [P, I, I, I, U64, U32, P, P, P, I64, P, P, P, SZ, P, P]),
     "aps_sample_mask_ex": (I, [P, I, I, I, U64, U32, P, I, I, P, P, P, I64, P, P, P, SZ, P, P]),
+    "aps_sample_mask_noalloc": (I, [P, I, I, I, U64, U32, P, I, I, P, P, P, I64, P, P, P, P]),
     "aps_fixture_render": (I, [P, I, P, P, I, I, I, I64, P, P]),
     "aps_scatter_samples": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P]),
     "aps_scatter_samples_ex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P]),

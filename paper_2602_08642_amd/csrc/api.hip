@@ -14,6 +14,7 @@ const char* aps_status_string(int status) {
     case APS_ERR_WORKSPACE: return "workspace missing or too small";
     case APS_ERR_HIP: return "HIP runtime error";
     case APS_ERR_ARG: return "scalar argument out of range";
+    case APS_ERR_TOO_LARGE: return "problem larger than the static scratch of a no-allocation entry point";
     default: return "unknown status";
   }
 }

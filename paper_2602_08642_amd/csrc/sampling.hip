@@ -5,6 +5,9 @@
 //   s-normalised scatter + pyramid         (Sec. 4.2 eq. stoch_rnoisy, Sec. 4.3 eqs.
 //                                           relaxed_holdout / h_factor, App. A eq. app-pyramid)
 //   renderer stand-in and feature assembly (inputs of the two networks)
+#include <atomic>
+#include <mutex>
+
 #include "aps_common.h"
 
 using namespace aps;
@@ -690,6 +693,91 @@ __global__ __launch_bounds__(256) void k_features_bwd(int kind, const float4* __
   }
 }
 
+// ------------------------------------------------------------------ static mask scratch
+// The no-allocation variant of the mask keeps its block sums and block offsets in this
+// file-scope array instead of a caller workspace.  Each device holds its own copy; host code
+// reaches it only through the address hipGetSymbolAddress returns for that device (the
+// array's name is a host-side stand-in, not a device address).
+constexpr size_t kMaskStaticPixels = size_t(1) << 25;  // 33.5M px: four 3840x2160 frames
+constexpr size_t kMaskStaticBlocks = kMaskStaticPixels / kMaskBlock;
+static __device__ __align__(256) int32_t scratch[2 * kMaskStaticBlocks];  // 1 MiB
+
+constexpr int kMaxDevices = 64;
+std::atomic<int32_t*> g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// The scratch address on the device `stream` belongs to (looked up once per device, with that
+// device current); nullptr if a HIP call fails.
+int32_t* mask_scratch(hipStream_t st) {
+  int dev = -1;
+  if (st) {
+    if (hipStreamGetDevice(st, &dev) != hipSuccess) return nullptr;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  int32_t* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (p) return p;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (p) return p;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+  if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+  void* addr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+  if (cur != dev && hipSetDevice(cur) != hipSuccess) return nullptr;
+  if (e != hipSuccess || !addr) return nullptr;
+  p = static_cast<int32_t*>(addr);
+  g_scratch_ptr[dev].store(p, std::memory_order_release);
+  return p;
+}
+
+// Counts, block sums, their scan and the compaction (eq. holdout); the two int32 arrays of
+// nb entries come from ws or, with use_static, from the device's static scratch.
+int sample_mask_impl(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                     const float* u_tex, int tex_size, int rounding, uint8_t* count,
+                     int32_t* pixel_offset, int32_t* sample_pixel, int64_t capacity,
+                     int32_t* total, float* p_out, void* ws, size_t ws_bytes, bool use_static,
+                     uint32_t* dev_status, void* stream) {
+  if (N < 0 || H < 0 || W < 0 || capacity < 0) return APS_ERR_SHAPE;
+  if (u_tex && (tex_size < 1 || tex_size > kMaxTexSize)) return APS_ERR_ARG;
+  if (rounding != APS_ROUND_STOCHASTIC && rounding != APS_ROUND_HOLDOUT &&
+      rounding != APS_ROUND_DETERMINISTIC)
+    return APS_ERR_ARG;
+  const size_t npix = (size_t)N * H * W;
+  if (npix > 0x7fffffffull) return APS_ERR_SHAPE;
+  if (use_static && npix > kMaskStaticPixels) return APS_ERR_TOO_LARGE;
+  if (!total) return APS_ERR_NULL;
+  hipStream_t st = as_stream(stream);
+  if (npix == 0) {  // a kernel, not a memset node: safe under stream capture
+    k_zero_i32<<<1, 64, 0, st>>>(total);
+    APS_LAUNCH_CHECK();
+    return APS_OK;
+  }
+  if (!s || !count || !pixel_offset || (!sample_pixel && capacity > 0)) return APS_ERR_NULL;
+  const int nb = (int)((npix + kMaskBlock - 1) / kMaskBlock);
+  int32_t* bsum;
+  if (use_static) {
+    bsum = mask_scratch(st);
+    if (!bsum) return APS_ERR_HIP;
+  } else {
+    if (!ws || ws_bytes < aps_sample_mask_workspace_size(N, H, W)) return APS_ERR_WORKSPACE;
+    bsum = static_cast<int32_t*>(ws);
+  }
+  // every entry of both arrays is written before it is read (k_mask_count writes all nb block
+  // sums, k_mask_scan all nb offsets): nothing has to start at zero
+  int32_t* boff = bsum + nb;
+  const USource us{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W};
+  k_mask_count<<<nb, kMaskBlock, 0, st>>>(s, (int)npix, seed, frame, us, rounding, count, p_out,
+                                          bsum, dev_status);
+  k_mask_scan<<<1, 1024, 0, st>>>(bsum, nb, boff, total);
+  k_mask_compact<<<nb, kMaskBlock, 0, st>>>(count, (int)npix, boff, pixel_offset, sample_pixel,
+                                            capacity, dev_status);
+  APS_LAUNCH_CHECK();
+  return APS_OK;
+}
+
 }  // namespace
 
 // ======================================================================== C ABI
@@ -745,33 +833,18 @@ int aps_sample_mask_ex(const float* s, int N, int H, int W, uint64_t seed, uint3
                        int32_t* pixel_offset, int32_t* sample_pixel, int64_t capacity,
                        int32_t* total, float* p_out, void* ws, size_t ws_bytes,
                        uint32_t* dev_status, void* stream) {
-  if (N < 0 || H < 0 || W < 0 || capacity < 0) return APS_ERR_SHAPE;
-  if (u_tex && (tex_size < 1 || tex_size > kMaxTexSize)) return APS_ERR_ARG;
-  if (rounding != APS_ROUND_STOCHASTIC && rounding != APS_ROUND_HOLDOUT &&
-      rounding != APS_ROUND_DETERMINISTIC)
-    return APS_ERR_ARG;
-  const size_t npix = (size_t)N * H * W;
-  if (npix > 0x7fffffffull) return APS_ERR_SHAPE;
-  if (!total) return APS_ERR_NULL;
-  hipStream_t st = as_stream(stream);
-  if (npix == 0) {  // a kernel, not a memset node: safe under stream capture
-    k_zero_i32<<<1, 64, 0, st>>>(total);
-    APS_LAUNCH_CHECK();
-    return APS_OK;
-  }
-  if (!s || !count || !pixel_offset || (!sample_pixel && capacity > 0)) return APS_ERR_NULL;
-  if (!ws || ws_bytes < aps_sample_mask_workspace_size(N, H, W)) return APS_ERR_WORKSPACE;
-  const int nb = (int)((npix + kMaskBlock - 1) / kMaskBlock);
-  int32_t* bsum = static_cast<int32_t*>(ws);
-  int32_t* boff = bsum + nb;
-  const USource us{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W};
-  k_mask_count<<<nb, kMaskBlock, 0, st>>>(s, (int)npix, seed, frame, us, rounding, count, p_out,
-                                          bsum, dev_status);
-  k_mask_scan<<<1, 1024, 0, st>>>(bsum, nb, boff, total);
-  k_mask_compact<<<nb, kMaskBlock, 0, st>>>(count, (int)npix, boff, pixel_offset, sample_pixel,
-                                            capacity, dev_status);
-  APS_LAUNCH_CHECK();
-  return APS_OK;
+  return sample_mask_impl(s, N, H, W, seed, frame, u_tex, tex_size, rounding, count, pixel_offset,
+                          sample_pixel, capacity, total, p_out, ws, ws_bytes, false, dev_status,
+                          stream);
+}
+
+int aps_sample_mask_noalloc(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
+                            const float* u_tex, int tex_size, int rounding, uint8_t* count,
+                            int32_t* pixel_offset, int32_t* sample_pixel, int64_t capacity,
+                            int32_t* total, float* p_out, uint32_t* dev_status, void* stream) {
+  return sample_mask_impl(s, N, H, W, seed, frame, u_tex, tex_size, rounding, count, pixel_offset,
+                          sample_pixel, capacity, total, p_out, nullptr, 0, true, dev_status,
+                          stream);
 }
 
 int aps_fixture_render(const float* pool, int J, const uint8_t* count,

@@ -129,6 +129,29 @@ def sample_mask(s, seed: int, frame: int, capacity: int | None = None, want_p=Fa
                 capacity=capacity)
 
 
+def sample_mask_noalloc(s, seed: int, frame: int, capacity: int | None = None, want_p=False,
+                        status=None, u_tex=None, rounding: str = "stochastic"):
+    """sample_mask through the entry point that takes no workspace (the library's static
+    scratch; at most 2^25 pixels)."""
+    _need(s, "s", _F32)
+    N, H, W = s.shape
+    dev = s.device
+    if capacity is None:
+        capacity = N * H * W * 2
+    count = torch.empty((N, H, W), dtype=torch.uint8, device=dev)
+    poff = torch.empty((N, H, W), dtype=torch.int32, device=dev)
+    spix = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    total = torch.empty(1, dtype=torch.int32, device=dev)
+    p = torch.empty_like(s) if want_p else None
+    tp, T = _tex(u_tex)
+    L.check(L.load().aps_sample_mask_noalloc(_p(s), N, H, W, seed, frame, tp, T, _ROUNDING[rounding],
+                                             _p(count), _p(poff), _p(spix), capacity, _p(total),
+                                             _p(p), _p(status), _stream()),
+            "sample_mask_noalloc")
+    return dict(count=count, pixel_offset=poff, sample_pixel=spix, total=total, p=p,
+                capacity=capacity)
+
+
 def fixture_render(pool, count, pixel_offset, capacity: int):
     _need(pool, "pool", _F32)
     N, H, W = count.shape

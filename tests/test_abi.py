@@ -58,3 +58,8 @@ def test_host_side_validation_without_gpu(lib):
     assert lib.aps_normalize_density(1, 1, 8, 8, 0.25, 0.125, 1, 1, 1, None, None) == 4
     # relaxed mode needs lambda >= 1
     assert lib.aps_scatter_samples(1, 1, 1, 1, 10, 1, 8, 8, 1, 1, 0.5, 0, 0, arr, None) == 6
+    # the no-allocation mask rejects problems beyond its static scratch (2^25 pixels) before
+    # any HIP call
+    assert lib.aps_sample_mask_noalloc(1, 5, 2160, 3840, 0, 0, None, 0, 0, 1, 1, 1, 10, 1, None,
+                                       None, None) == 7
+    assert lib.aps_status_string(7).startswith(b"problem larger")
