@@ -364,6 +364,60 @@ int aps_denoise_pyramid_bwd(const float* const* L, const void* const* logits, in
                             const int* gstride, float* const* grad_L, float* grad_prev, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* Backward of aps_reproject (App. A eq. app-recon-full: the kt gather of the bilinearly warped
+ * previous output, weighted by the level-0 joint softmax).  grad_accum [N,H,W,4] float32 is
+ * dLoss/d(accum_out) after the call; the gradient w.r.t. the accum_out input is grad_accum
+ * itself (the term is added), so nothing is written for it.
+ *   grad_logits0 [N,H,W,gstride] (grad_dtype F32|BF16; written, channels >= K zeroed):
+ *     w_k (<g, v_k> [k in the kt block] - <g, T>) over all K = KD^2 (+ KU^2) + KT^2 channels,
+ *     the softmax being shared with the level's other terms (eq. app-softmax-full);
+ *   grad_prev [N,H,W,4] float32 (accumulated, nullable): the transpose of the kt gather (a
+ *     gather over each pixel's edge-clamped preimages) and of the bilinear warp (float atomics,
+ *     order not fixed).
+ * Motion vectors are not differentiated.  Workspace: the normalised weights, N*H*W*K floats.
+ * Other arguments and errors as aps_reproject; APS_ERR_UNSUPPORTED for another grad_dtype. */
+size_t aps_reproject_bwd_workspace_size(int N, int H, int W, int KD, int KU, int KT,
+                                        int has_upsample);
+int aps_reproject_bwd(const float* prev, const float* mv, const void* logits0, int logit_dtype,
+                      int kstride, int KD, int KU, int KT, int has_upsample, int N, int H, int W,
+                      const float* grad_accum, void* grad_logits0, int grad_dtype, int gstride,
+                      float* grad_prev, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of aps_upsample (App. A eq. app-upsample: the ku gather of the coarser
+ * reconstructed level around each pixel's parent, with the level's joint softmax).
+ *   grad_logits [N,H,W,gstride] (written, channels >= K zeroed): w_k (<g, v_k> [k in the ku
+ *     block] - <g, U>) over all K = KD^2 + KU^2 (+ KT^2) channels;
+ *   grad_coarse [N,H/2,W/2,4] float32 (written): for each coarse pixel the sum over the fine
+ *     pixels and ku taps that read it (gather form, deterministic).
+ * The accum_out input passes grad_accum through unchanged (nothing written).  Workspace:
+ * N*H*W*K floats.  Other arguments and errors as aps_upsample. */
+size_t aps_upsample_bwd_workspace_size(int N, int H, int W, int KD, int KU, int KT,
+                                       int has_temporal);
+int aps_upsample_bwd(const float* coarse, const void* logits, int logit_dtype, int kstride, int KD,
+                     int KU, int KT, int has_temporal, int N, int H, int W,
+                     const float* grad_accum, void* grad_logits, int grad_dtype, int gstride,
+                     float* grad_coarse, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of aps_density_predict (Sec. 3, Overview: the sampler network and the budget
+ * normalisation; Sec. 4.3: the density is trained through the relaxed sampling step, whose
+ * gradient dLoss/ds aps_scatter_samples_bwd gives).  The three layers are recomputed layer by
+ * layer from feat (nothing is kept from the forward), then:
+ *   dLoss/dz = aps_normalize_density_bwd of grad_s [N,H,W] float32;
+ *   grad_w[i] [Cout][k][k][Cin] float32 and grad_b[i] [Cout] float32 (written, i = 0, 1, 2):
+ *     weight and bias gradients (MFMA, fixed-order split reduction: deterministic), the
+ *     hidden layers' gradients masked by their ReLU outputs;
+ *   grad_feat [N,H,W,C] in the net dtype (written, nullable): the input gradient.
+ * packed_dgrad[i]: layer i's data-gradient operator (aps_conv_pack_weights_dgrad of its
+ * float32 weights, in the net dtype); packed_dgrad[0] may be NULL when grad_feat is NULL.  In
+ * bf16 dLoss/dz and the hidden gradients are rounded to bf16 between layers.  The layers must
+ * have the shapes aps_density_predict takes (C -> c0 ReLU -> c1 ReLU -> 1 linear), else
+ * APS_ERR_SHAPE. */
+size_t aps_density_predict_bwd_workspace_size(const aps_net* net, int N, int H, int W);
+int aps_density_predict_bwd(const aps_net* net, const void* const* packed_dgrad, const void* feat,
+                            int N, int H, int W, int C, float budget_spp, float uniform_frac,
+                            const float* grad_s, float* const* grad_w, float* const* grad_b,
+                            void* grad_feat, void* ws, size_t ws_bytes, void* stream);
+
 /* Scatter backward (Sec. 4.2 eq. stoch_rnoisy, Sec. 4.3 eq. relaxed_holdout): grad_s (written,
  * or accumulated when accumulate != 0) = <dLoss/dL0, dL0/ds> with
  *   dL0/ds = -L0/s + (S_holdout/s) dw/dp,  dw/dp = h lambda u / p^2 inside the relaxed ramp,

@@ -70,6 +70,12 @@ SIGNATURES = {
     "aps_denoise_pyramid_bwd_workspace_size": (SZ, [I, I, I, I, I, I, I, I]),
     "aps_denoise_pyramid_bwd": (I, [P, P, I, P, I, I, I, I, P, P, I, I, I, P, P, I, P, P, P, P,
                                     SZ, P]),
+    "aps_reproject_bwd_workspace_size": (SZ, [I, I, I, I, I, I, I]),
+    "aps_reproject_bwd": (I, [P, P, P, I, I, I, I, I, I, I, I, I, P, P, I, I, P, P, SZ, P]),
+    "aps_upsample_bwd_workspace_size": (SZ, [I, I, I, I, I, I, I]),
+    "aps_upsample_bwd": (I, [P, P, I, I, I, I, I, I, I, I, I, P, P, I, I, P, P, SZ, P]),
+    "aps_density_predict_bwd_workspace_size": (SZ, [C.POINTER(NetDesc), I, I, I]),
+    "aps_density_predict_bwd": (I, [C.POINTER(NetDesc), P, P, I, I, I, I, F, F, P, P, P, P, P, SZ, P]),
     "aps_scatter_samples_bwd": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, P, I, P]),
     "aps_scatter_samples_bwd_ex": (I, [P, P, P, P, I64, I, I, I, I, I, F, U64, U32, P, I, P, P, P, I, P]),
     "aps_normalize_bwd_workspace_size": (SZ, [I, I, I]),

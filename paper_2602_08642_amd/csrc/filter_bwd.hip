@@ -77,6 +77,20 @@ __global__ __launch_bounds__(256) void k_level_bwd(BwdArgs b) {
   for_each_tap<KD, KU, KT, HU, HT>(a, Ls, Cs, Ts, tx, ty, x, y, x0, y0, [&](int k, float4 v) {
     gstore(gl + k, z[k] * (g.x * v.x + g.y * v.y + g.z * v.z - gy));
   });
+  // blocks of the joint softmax whose term is not part of this output (the standalone
+  // reproject and upsample terms): only their share of the normalisation, -w_k <g, y>
+  if (!a.eval_g) {
+#pragma unroll
+    for (int k = 0; k < G::ND; ++k) gstore(gl + k, -z[k] * gy);
+  }
+  if (HU && !a.eval_u) {
+#pragma unroll
+    for (int k = G::ND; k < G::ND + G::NU; ++k) gstore(gl + k, -z[k] * gy);
+  }
+  if (HT && !a.eval_t) {
+#pragma unroll
+    for (int k = G::ND + G::NU; k < NK; ++k) gstore(gl + k, -z[k] * gy);
+  }
   for (int k = NK; k < b.gstride; ++k) gstore(gl + k, 0.f);
   float* wb = b.wbuf + pix * NK;
 #pragma unroll
@@ -352,6 +366,84 @@ int aps_denoise_pyramid_bwd(const float* const* L, const void* const* logits, in
     }
   }
   return APS_OK;
+}
+
+// ---- standalone terms: reproject (kt block) and upsample (ku block) ------------------------
+
+size_t aps_reproject_bwd_workspace_size(int N, int H, int W, int KD, int KU, int KT,
+                                        int has_upsample) {
+  const int nk = KD * KD + (has_upsample ? KU * KU : 0) + KT * KT;
+  return align256((size_t)N * H * W * nk * sizeof(float)) + 256;
+}
+
+int aps_reproject_bwd(const float* prev, const float* mv, const void* logits0, int logit_dtype,
+                      int kstride, int KD, int KU, int KT, int has_upsample, int N, int H, int W,
+                      const float* grad_accum, void* grad_logits0, int grad_dtype, int gstride,
+                      float* grad_prev, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if (has_upsample && (H % 2 || W % 2)) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!prev || !mv || !logits0 || !grad_accum || !grad_logits0) return APS_ERR_NULL;
+  if (grad_dtype != APS_F32 && grad_dtype != APS_BF16) return APS_ERR_UNSUPPORTED;
+  const int nk = KD * KD + (has_upsample ? KU * KU : 0) + KT * KT;
+  if (!kstride_ok(kstride, nk, logit_dtype) || gstride < nk) return APS_ERR_SHAPE;
+  if (!ws || ws_bytes < aps_reproject_bwd_workspace_size(N, H, W, KD, KU, KT, has_upsample))
+    return APS_ERR_WORKSPACE;
+  hipStream_t st = as_stream(stream);
+  BwdArgs b{};
+  b.f.logits = logits0;
+  b.f.kstride = kstride;
+  b.f.prev = reinterpret_cast<const float4*>(prev);
+  b.f.mv = reinterpret_cast<const float2*>(mv);
+  b.f.H = H;
+  b.f.W = W;
+  b.f.eval_t = 1;
+  b.gout = reinterpret_cast<const float4*>(grad_accum);
+  b.glogits = grad_logits0;
+  b.gstride = gstride;
+  b.wbuf = static_cast<float*>(ws);
+  int r = launch_bwd(b, logit_dtype, grad_dtype, KD, KU, KT, has_upsample != 0, true, N, st);
+  if (r != APS_OK) return r;
+  if (grad_prev)
+    r = launch_warp_T(KT, b.wbuf, nk, KD * KD + (has_upsample ? KU * KU : 0), b.gout, b.f.mv, N, H,
+                      W, grad_prev, st);
+  return r;
+}
+
+size_t aps_upsample_bwd_workspace_size(int N, int H, int W, int KD, int KU, int KT,
+                                       int has_temporal) {
+  const int nk = KD * KD + KU * KU + (has_temporal ? KT * KT : 0);
+  return align256((size_t)N * H * W * nk * sizeof(float)) + 256;
+}
+
+int aps_upsample_bwd(const float* coarse, const void* logits, int logit_dtype, int kstride, int KD,
+                     int KU, int KT, int has_temporal, int N, int H, int W,
+                     const float* grad_accum, void* grad_logits, int grad_dtype, int gstride,
+                     float* grad_coarse, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 0 || H < 0 || W < 0 || H % 2 || W % 2) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!coarse || !logits || !grad_accum || !grad_logits || !grad_coarse) return APS_ERR_NULL;
+  if (grad_dtype != APS_F32 && grad_dtype != APS_BF16) return APS_ERR_UNSUPPORTED;
+  const int nk = KD * KD + KU * KU + (has_temporal ? KT * KT : 0);
+  if (!kstride_ok(kstride, nk, logit_dtype) || gstride < nk) return APS_ERR_SHAPE;
+  if (!ws || ws_bytes < aps_upsample_bwd_workspace_size(N, H, W, KD, KU, KT, has_temporal))
+    return APS_ERR_WORKSPACE;
+  hipStream_t st = as_stream(stream);
+  BwdArgs b{};
+  b.f.logits = logits;
+  b.f.kstride = kstride;
+  b.f.coarse = reinterpret_cast<const float4*>(coarse);
+  b.f.H = H;
+  b.f.W = W;
+  b.f.eval_u = 1;
+  b.gout = reinterpret_cast<const float4*>(grad_accum);
+  b.glogits = grad_logits;
+  b.gstride = gstride;
+  b.wbuf = static_cast<float*>(ws);
+  const int r = launch_bwd(b, logit_dtype, grad_dtype, KD, KU, KT, true, has_temporal != 0, N, st);
+  if (r != APS_OK) return r;
+  return launch_up_T(KU, b.wbuf, nk, KD * KD, b.gout, N, H, W,
+                     reinterpret_cast<float4*>(grad_coarse), st);
 }
 
 }  // extern "C"

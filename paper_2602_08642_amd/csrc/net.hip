@@ -141,6 +141,93 @@ int aps_density_predict(const aps_net* net, const void* feat, int N, int H, int 
                                aps_normalize_workspace_size(N, H, W), dev_status, stream);
 }
 
+size_t aps_density_predict_bwd_workspace_size(const aps_net* net, int N, int H, int W) {
+  if (!net || net->n_layers != 3) return 0;
+  const aps_conv_layer* L = net->layer;
+  const size_t px = (size_t)N * H * W, e = esize(net->dtype);
+  const int c0 = L[0].cout, c1 = L[1].cout;
+  const int ld2 = net->dtype == APS_BF16 ? 8 : 4;  // padded 1-channel gradient (16-byte rows)
+  size_t wg = 0;
+  for (int i = 0; i < 3; ++i) {
+    const size_t b = aps_conv2d_bwd_weight_workspace_size(N, H, W, L[i].cin, 0, L[i].cout, L[i].ksize);
+    if (b > wg) wg = b;
+  }
+  return align256(px * c0 * e) + align256(px * c1 * e)          // a0, a1 (post-ReLU)
+         + align256(px * 4) + align256(px * 4)                  // z, dLoss/dz
+         + align256(px * ld2 * e)                               // dLoss/dz as the last layer's dy
+         + align256(px * c1 * e) + align256(px * c0 * e)        // dLoss/da1, dLoss/da0
+         + align256(aps_normalize_bwd_workspace_size(N, H, W)) + align256(wg)
+         + 256;
+}
+
+int aps_density_predict_bwd(const aps_net* net, const void* const* packed_dgrad, const void* feat,
+                            int N, int H, int W, int C, float budget_spp, float uniform_frac,
+                            const float* grad_s, float* const* grad_w, float* const* grad_b,
+                            void* grad_feat, void* ws, size_t ws_bytes, void* stream) {
+  if (!net) return APS_ERR_NULL;
+  if (net->n_layers != 3) return APS_ERR_SHAPE;
+  if (N < 0 || H < 0 || W < 0) return APS_ERR_SHAPE;
+  if ((size_t)N * H * W == 0) return APS_OK;
+  if (!feat || !grad_s || !grad_w || !grad_b || !packed_dgrad) return APS_ERR_NULL;
+  const int dt = net->dtype;
+  if (dt != APS_F32 && dt != APS_BF16) return APS_ERR_UNSUPPORTED;
+  const aps_conv_layer* L = net->layer;
+  for (int i = 0; i < 3; ++i) {
+    if (!L[i].w || !L[i].b || !grad_w[i] || !grad_b[i]) return APS_ERR_NULL;
+    if (i > 0 && !packed_dgrad[i]) return APS_ERR_NULL;
+  }
+  if (grad_feat && !packed_dgrad[0]) return APS_ERR_NULL;
+  if (L[0].cin != C || L[1].cin != L[0].cout || L[2].cin != L[1].cout || L[2].cout != 1 ||
+      !L[0].relu || !L[1].relu || L[2].relu)
+    return APS_ERR_SHAPE;
+  if (!ws || ws_bytes < aps_density_predict_bwd_workspace_size(net, N, H, W)) return APS_ERR_WORKSPACE;
+  const size_t px = (size_t)N * H * W, e = esize(dt);
+  const int c0 = L[0].cout, c1 = L[1].cout;
+  const int ld2 = dt == APS_BF16 ? 8 : 4;
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) {
+    void* r = p;
+    p += align256(bytes);
+    return r;
+  };
+  void* a0 = take(px * c0 * e);
+  void* a1 = take(px * c1 * e);
+  float* z = static_cast<float*>(take(px * 4));
+  float* gz = static_cast<float*>(take(px * 4));
+  void* dy2 = take(px * ld2 * e);
+  void* da1 = take(px * c1 * e);
+  void* da0 = take(px * c0 * e);
+  const size_t nws = aps_normalize_bwd_workspace_size(N, H, W);
+  void* nw = take(nws);
+  void* wg = p;
+  const size_t wg_bytes = ws_bytes - (size_t)(p - static_cast<char*>(ws));
+  // forward recomputation, layer by layer (the post-ReLU activations are the ReLU masks and
+  // the inputs of the weight gradients)
+  APS_TRY(conv(L[0], feat, nullptr, N, H, W, C, 0, APS_CONV_DIRECT, dt, a0, c0, dt, stream));
+  APS_TRY(conv(L[1], a0, nullptr, N, H, W, c0, 0, APS_CONV_DIRECT, dt, a1, c1, dt, stream));
+  APS_TRY(conv(L[2], a1, nullptr, N, H, W, c1, 0, APS_CONV_DIRECT, dt, z, 1, APS_F32, stream));
+  // budget normalisation: dLoss/dz
+  APS_TRY(aps_normalize_density_bwd(z, N, H, W, budget_spp, uniform_frac, grad_s, gz, nw, nws,
+                                    stream));
+  // output layer (linear): dLoss/dz in the network dtype, padded to a 16-byte row
+  APS_TRY(aps_copy_channels(gz, APS_F32, 1, dy2, dt, ld2, (int64_t)px, 1, stream));
+  APS_TRY(aps_conv2d_bwd_weight(a1, nullptr, APS_CONV_DIRECT, N, H, W, c1, 0, dy2, nullptr, ld2, 1,
+                                L[2].ksize, dt, grad_w[2], grad_b[2], wg, wg_bytes, stream));
+  APS_TRY(aps_conv2d_bwd_data(dy2, nullptr, ld2, N, H, W, 1, packed_dgrad[2], L[2].ksize, c1, dt,
+                              da1, stream));
+  // hidden layers: the gradient masked by their ReLU outputs
+  APS_TRY(aps_conv2d_bwd_weight(a0, nullptr, APS_CONV_DIRECT, N, H, W, c0, 0, da1, a1, c1, c1,
+                                L[1].ksize, dt, grad_w[1], grad_b[1], wg, wg_bytes, stream));
+  APS_TRY(aps_conv2d_bwd_data(da1, a1, c1, N, H, W, c1, packed_dgrad[1], L[1].ksize, c0, dt, da0,
+                              stream));
+  APS_TRY(aps_conv2d_bwd_weight(feat, nullptr, APS_CONV_DIRECT, N, H, W, C, 0, da0, a0, c0, c0,
+                                L[0].ksize, dt, grad_w[0], grad_b[0], wg, wg_bytes, stream));
+  if (grad_feat)
+    APS_TRY(aps_conv2d_bwd_data(da0, a0, c0, N, H, W, c0, packed_dgrad[0], L[0].ksize, C, dt,
+                                grad_feat, stream));
+  return APS_OK;
+}
+
 int aps_avgpool2(const void* x, int N, int H, int W, int C, int dtype, void* y, void* stream) {
   if (N < 0 || H < 0 || W < 0 || C <= 0 || H % 2 || W % 2 || C % 4) return APS_ERR_SHAPE;
   if (dtype != APS_F32 && dtype != APS_BF16) return APS_ERR_UNSUPPORTED;

@@ -436,6 +436,64 @@ def upsample(coarse, logits, KD, KU, KT, has_temporal: bool, accum=None):
 
 # ------------------------------------------------------------------ backward (a10)
 
+def reproject_bwd(prev, mv, logits0, KD, KU, KT, has_upsample: bool, grad_accum, grad_dtype=None,
+                  want_prev: bool = True):
+    """-> (grad_logits0 [same shape as logits0], grad_prev or None) of the reproject term."""
+    _need(prev, "prev", _F32)
+    _need(grad_accum, "grad_accum", _F32)
+    N, H, W, _ = prev.shape
+    gdt = grad_dtype or logits0.dtype
+    glog = torch.empty(logits0.shape, dtype=gdt, device=prev.device)
+    gprev = torch.zeros_like(prev) if want_prev else None
+    lib = L.load()
+    nb = lib.aps_reproject_bwd_workspace_size(N, H, W, KD, KU, KT, int(has_upsample))
+    ws = WS.get(nb, prev.device)
+    L.check(lib.aps_reproject_bwd(_p(prev), _p(mv), _p(logits0), _dt(logits0.dtype), logits0.shape[-1],
+                                  KD, KU, KT, int(has_upsample), N, H, W, _p(grad_accum), _p(glog),
+                                  _dt(gdt), glog.shape[-1], _p(gprev), _p(ws), nb, _stream()),
+            "reproject_bwd")
+    return glog, gprev
+
+
+def upsample_bwd(coarse, logits, KD, KU, KT, has_temporal: bool, grad_accum, grad_dtype=None):
+    """-> (grad_logits [same shape as logits], grad_coarse) of the upsampling term."""
+    _need(coarse, "coarse", _F32)
+    _need(grad_accum, "grad_accum", _F32)
+    N, H, W = logits.shape[0], logits.shape[1], logits.shape[2]
+    gdt = grad_dtype or logits.dtype
+    glog = torch.empty(logits.shape, dtype=gdt, device=coarse.device)
+    gc = torch.empty_like(coarse)
+    lib = L.load()
+    nb = lib.aps_upsample_bwd_workspace_size(N, H, W, KD, KU, KT, int(has_temporal))
+    ws = WS.get(nb, coarse.device)
+    L.check(lib.aps_upsample_bwd(_p(coarse), _p(logits), _dt(logits.dtype), logits.shape[-1], KD, KU,
+                                 KT, int(has_temporal), N, H, W, _p(grad_accum), _p(glog), _dt(gdt),
+                                 glog.shape[-1], _p(gc), _p(ws), nb, _stream()), "upsample_bwd")
+    return glog, gc
+
+
+def density_predict_bwd(net: Net, feat, budget: float, grad_s, uniform_frac: float = 1.0 / 8.0,
+                        want_feat: bool = True):
+    """-> ({layer name: (dw [cout,k,k,cin] f32, db [cout] f32)}, grad_feat or None)."""
+    _need(feat, "feat", net.dtype)
+    _need(grad_s, "grad_s", _F32)
+    N, H, W, Cf = feat.shape
+    names = [l["name"] for l in net.spec]
+    pk = [pack_dgrad(l, net.master[l["name"]][0], net.dtype) for l in net.spec]
+    gw = [torch.empty((l["cout"], l["k"], l["k"], l["cin"]), dtype=_F32, device=feat.device)
+          for l in net.spec]
+    gb = [torch.empty(l["cout"], dtype=_F32, device=feat.device) for l in net.spec]
+    gf = torch.empty_like(feat) if want_feat else None
+    lib = L.load()
+    nb = lib.aps_density_predict_bwd_workspace_size(C.byref(net.desc), N, H, W)
+    ws = WS.get(nb, feat.device)
+    arr = lambda ts: (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+    L.check(lib.aps_density_predict_bwd(C.byref(net.desc), arr(pk), _p(feat), N, H, W, Cf, budget,
+                                        uniform_frac, _p(grad_s), arr(gw), arr(gb), _p(gf), _p(ws), nb,
+                                        _stream()), "density_predict_bwd")
+    return {n: (w, b) for n, w, b in zip(names, gw, gb)}, gf
+
+
 def denoise_pyramid_bwd(Ls, logits, KD: int, KU: int, KT: int, prev, mv, grad_out,
                         grad_dtype=None, want_prev: bool = True):
     """-> (grad_logits list [same shape as logits], grad_L list, grad_prev or None)."""

@@ -61,6 +61,7 @@ def _seed(*a):
     (1, 32, 48, 3, 5, 3, 3, True, torch.float32),
     (2, 24, 40, 2, 5, 3, 3, False, torch.float32),
     (1, 32, 32, 4, 7, 3, 3, True, torch.float32),
+    (1, 32, 48, 4, 7, 3, 3, True, torch.bfloat16),
     (1, 16, 24, 2, 5, 2, 5, True, torch.float32),
     (1, 24, 32, 3, 3, 3, 3, True, torch.bfloat16),
 ])

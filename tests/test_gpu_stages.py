@@ -201,6 +201,7 @@ def _rand_inputs(N, H, W, levels, KD, KU, KT, temporal, seed, ldtype):
     (2, 64, 96, 3, 5, 3, 3, True, torch.float32),
     (1, 64, 96, 3, 5, 3, 3, True, torch.bfloat16),
     (1, 48, 80, 4, 7, 3, 3, True, torch.float32),
+    (1, 48, 80, 4, 7, 3, 3, True, torch.bfloat16),    # C5's level kernels: bf16 logits, 67-way softmax
     (1, 48, 64, 4, 5, 2, 5, True, torch.float32),
     (1, 40, 56, 2, 3, 3, 3, True, torch.bfloat16),
 ])
