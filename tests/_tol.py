@@ -32,3 +32,4 @@ def assert_mag_close(y, r, mag, tol, floor=1e-30, what=""):
 def rel_norm(y, r):
     y, r = to_np(y), to_np(r)
     return float(np.linalg.norm(y - r) / max(np.linalg.norm(r), 1e-300))
+

@@ -9,7 +9,8 @@ import torch
 import procgen
 from oracle import density as odens
 from oracle import unet as ounet
-from tests._tol import rel_norm
+from tests import _nets
+from tests._tol import assert_mag_close
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -22,22 +23,41 @@ def ops():
     return o
 
 
-@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.bfloat16, 2e-2)])
+E2E = {torch.bfloat16: (2e-2, 6e-2), torch.float32: (1e-5, 1e-4)}
+LAYER_TOL = {torch.bfloat16: 2e-2, torch.float32: 1e-5}
+
+
+def _wq(w, dtype):
+    return {k: (torch.tensor(a).to(dtype).double(), torch.tensor(b).double()) for k, (a, b) in w.items()}
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("heads", [[43, 34, 25], [67, 58, 58, 49]])
-def test_unet_matches_oracle(ops, dtype, tol, heads):
+def test_unet_matches_oracle(ops, dtype, heads):
+    """Stage-wise and end to end (tests/_nets.py), and the fused entry point against the chain
+    of single-layer calls: bit for bit in bf16, to float32 rounding in fp32 (the fused heads sum
+    the 1x1 product in another order)."""
     spec = procgen.unet_spec(16, heads)
     w = procgen.init_weights(spec, 11)
     net = ops.Net(spec, w, dtype, DEV)
     g = torch.Generator().manual_seed(1)
     x = torch.randn(2, 48, 64, 16, generator=g)
     x[..., 15] = 0
-    logits = ops.kernel_predict(net, x.to(DEV).to(dtype), heads, dtype)
-    # oracle on the values the GPU saw (bf16 inputs and weights widened exactly)
-    wq = {k: (torch.tensor(a).to(dtype).double(), torch.tensor(b).double()) for k, (a, b) in w.items()}
-    ref = ounet.unet_forward(x.to(dtype).double(), wq, len(heads))
+    xd = x.to(DEV).to(dtype)
+    logits = ops.kernel_predict(net, xd, heads, dtype)
+    rec, chain = _nets.unet_chain(ops, net, xd, heads, dtype)
+    what = f"unet {str(dtype)[6:]} {heads}"
     for l, K in enumerate(heads):
-        e = rel_norm(logits[l][..., :K].float().cpu(), ref[l])
-        assert e < tol, (l, e)
+        if dtype == torch.bfloat16:
+            assert torch.equal(logits[l][..., :K], chain[l][..., :K]), l
+        else:
+            c = chain[l][..., :K].cpu()
+            assert_mag_close(logits[l][..., :K].cpu(), c, c.abs() + float(c.abs().mean()), 1e-6,
+                             what=f"{what} fused vs chain head {l}")
+    wq = _wq(w, dtype)
+    _nets.check_layers(rec, wq, {l["name"]: l["relu"] for l in spec}, LAYER_TOL[dtype], what)
+    ref = ounet.unet_forward(x.to(dtype).double(), wq, len(heads))
+    _nets.check_end_to_end([t.cpu() for t in logits], ref, heads, *E2E[dtype], what=what)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
@@ -70,20 +90,24 @@ def test_fused_head_bit_identical(ops, dtype, cout, K):
 
 
 @pytest.mark.parametrize("cin", [8, 16])
-@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.bfloat16, 2e-2)])
-def test_sampler_cnn_matches_oracle(ops, cin, dtype, tol):
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_sampler_cnn_matches_oracle(ops, cin, dtype):
     spec = procgen.density_cnn_spec(cin)
     w = procgen.init_weights(spec, 5)
     net = ops.Net(spec, w, dtype, DEV)
     g = torch.Generator().manual_seed(2 + cin)
     x = torch.rand(2, 40, 56, cin, generator=g)
-    z, s = ops.density_predict(net, x.to(DEV).to(dtype), 0.25)
-    layers = [(torch.tensor(w[l["name"]][0]).to(dtype).double(), torch.tensor(w[l["name"]][1], dtype=torch.float64),
-               l["relu"]) for l in spec]
+    xd = x.to(DEV).to(dtype)
+    z, s = ops.density_predict(net, xd, 0.25)
+    rec, _ = _nets.sampler_chain(ops, net, xd)
+    wq = _wq(w, dtype)
+    what = f"sampler {cin} {str(dtype)[6:]}"
+    _nets.check_layers(rec, wq, {l["name"]: l["relu"] for l in spec}, LAYER_TOL[dtype], what)
+    layers = [(wq[l["name"]][0], wq[l["name"]][1], l["relu"]) for l in spec]
     zr = odens.cnn_forward(x.to(dtype).double(), layers)[..., 0]
-    assert rel_norm(z.cpu(), zr) < tol
+    _nets.check_end_to_end([z.cpu()], [zr], [0], *E2E[dtype], what=what)
     sr = odens.normalise(z.double().cpu(), 0.25)
-    assert rel_norm(s.cpu(), sr) < 1e-6
+    assert_mag_close(s.cpu(), sr, sr, 1e-5, what="normalisation")
 
 
 @pytest.mark.parametrize("cin", [8, 16])
@@ -199,6 +223,8 @@ def test_conv1x1_matches_oracle(ops, dtype, odt, tol, cin, cout, mode):
     x64 = xin.to(dtype).double()
     if mode == "pool2":   # the kernel rounds the pooled input to the storage type
         x64 = ounet.avgpool2(x64).to(dtype).double()
-    ref = odens.conv2d_nhwc(x64, w.to(dtype).double(), b.double())
+    w64 = w.to(dtype).double()
+    ref = odens.conv2d_nhwc(x64, w64, b.double())
+    mag = odens.conv2d_nhwc(x64.abs(), w64.abs(), b.double().abs())
     got = y[..., :cout].double().cpu()
-    assert float((got - ref).norm() / ref.norm()) < tol
+    assert_mag_close(got, ref, mag, tol, what=f"1x1 {cin}->{cout} {mode}")
