@@ -207,14 +207,15 @@ __device__ inline void store_out<uint16_t>(uint16_t* p, int ldy, int co0, int Co
 constexpr int kWaitVm0 = 0x0F70;
 
 // LDS the fused head's epilogue needs, in elements of the tile type T: per wave a [16 px][16 TM
-// ch] re-layout region (row pitch 16 TM + 8 or + 4), then per wave a [16 px][<= 64 ch] staging
+// ch] re-layout region (row pitch 16 TM + 8 or + 4), then per wave a [16 px][<= 16 HM ch] staging
 // region for the head outputs (type TO).  The kernels size their input tile at least this large.
-template <typename T, typename TO, int TM>
+// HM = head m-tiles (4: up to 64 logits, 5: up to 80); 0 = no fused head.
+template <typename T, typename TO, int TM, int HM>
 constexpr int head_lds_elems() {
-  return 4 * 16 * (TM * 16 + (sizeof(T) == 2 ? 8 : 4)) + 4 * 16 * 64 * (int)(sizeof(TO) / sizeof(T));
+  return 4 * 16 * (TM * 16 + (sizeof(T) == 2 ? 8 : 4)) + 4 * 16 * 16 * HM * (int)(sizeof(TO) / sizeof(T));
 }
 
-template <typename T, typename TO, int TM, int TN, bool HEAD, bool BIAS_IN_ACC = false>
+template <typename T, typename TO, int TM, int TN, int HEAD, bool BIAS_IN_ACC = false>
 __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], int row0, int tx0,
                                      int cob, int n, int lane, int wave, T* Xs) {
   TO* y = static_cast<TO*>(a.y);
@@ -256,17 +257,17 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
     // logits is contiguous in memory, so the wave writes it with 16-byte vector stores to
     // consecutive addresses (channels in [hK, hldy) as zeros) instead of one 8- or 16-byte piece
     // per lane and 16-channel group at the pixel stride, which measured about twice as slow.
-    constexpr int CC = TM * 16, YP = CC + (sizeof(T) == 2 ? 8 : 4);
+    constexpr int CC = TM * 16, YP = CC + (sizeof(T) == 2 ? 8 : 4), HM = HEAD;
     T* Ys = Xs + wave * 16 * YP;
-    TO* Os = reinterpret_cast<TO*>(Xs + 4 * 16 * YP) + wave * 16 * 64;
-    const bool staged = a.hldy <= 64 && (a.hldy * (int)sizeof(TO)) % 16 == 0 &&
+    TO* Os = reinterpret_cast<TO*>(Xs + 4 * 16 * YP) + wave * 16 * 16 * HM;
+    const bool staged = a.hldy <= 16 * HM && (a.hldy * (int)sizeof(TO)) % 16 == 0 &&
                         (reinterpret_cast<uintptr_t>(a.hy) & 15) == 0;
     const int npx = a.W - tx0 < 16 ? a.W - tx0 : 16;
     const T* hw = static_cast<const T*>(a.hw);
     TO* hy = static_cast<TO*>(a.hy);
-    Frag<T> hwf[4][TM / 2];
+    Frag<T> hwf[HM][TM / 2];
 #pragma unroll
-    for (int mh = 0; mh < 4; ++mh)
+    for (int mh = 0; mh < HM; ++mh)
 #pragma unroll
       for (int cc = 0; cc < TM / 2; ++cc)
         if (mh * 16 < a.hK) frag_load(hwf[mh][cc], hw + ((((size_t)mh * (TM / 2)) + cc) * 64 + lane) * 8);
@@ -274,9 +275,9 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
     // and the head weights here.  Left to the compiler, the wait for a value loaded under a
     // branch is placed at each use inside the later (branching) store code, and as vmcnt also
     // counts stores, every one of those waits would drain all stores issued before it.
-    float hb[4][4];
+    float hb[HM][4];
 #pragma unroll
-    for (int mh = 0; mh < 4; ++mh)
+    for (int mh = 0; mh < HM; ++mh)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = mh * 16 + 4 * (lane >> 4) + q;
@@ -312,7 +313,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
       for (int cc = 0; cc < TM / 2; ++cc) frag_load(bf[cc], Ys + (lane & 15) * YP + 32 * cc + 8 * (lane >> 4));
       if (staged) {
 #pragma unroll
-        for (int mh = 0; mh < 4; ++mh) {
+        for (int mh = 0; mh < HM; ++mh) {
           const int k0 = mh * 16 + 4 * (lane >> 4);
           if (mh * 16 >= a.hldy) break;
           f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -351,7 +352,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
         }
       } else {
 #pragma unroll
-        for (int mh = 0; mh < 4; ++mh) {
+        for (int mh = 0; mh < HM; ++mh) {
           if (mh * 16 >= a.hK) break;
           f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -377,13 +378,13 @@ __device__ inline void conv_epilogue(const ConvArgs& a, f32x4 (&acc)[TM][TN], in
 // one tap per MFMA step.  CG = 1 or 2 (inputs of at most 8 or 16 channels, a single chunk): K
 // enumerates (tap, group) pairs, so one MFMA step covers 4 / CG taps and no MFMA work is
 // spent on channel padding; lane group q of step s takes pair p = 4 s + q.
-template <typename T, typename TO, int KS, int TM, int TN, int CG, bool HEAD = false>
+template <typename T, typename TO, int KS, int TM, int TN, int CG, int HEAD = 0>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   constexpr int R = KS / 2;
   constexpr int TH = 4 * TN, TWp = 16;
   constexpr int SW = TWp + 2 * R, SH = TH + 2 * R;
   constexpr int PS = sizeof(T) == 2 ? 40 : 36;  // padded LDS pixel stride (elements)
-  constexpr int XS_HEAD = HEAD ? head_lds_elems<T, TO, TM>() : 0;
+  constexpr int XS_HEAD = HEAD ? head_lds_elems<T, TO, TM, HEAD>() : 0;
   __shared__ __attribute__((aligned(16))) T Xs[SH * SW * PS > XS_HEAD ? SH * SW * PS : XS_HEAD];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -473,12 +474,12 @@ constexpr uint32_t kNoPixel = 0xffffffffu;
 // bf16 y > 0 (positive, finite or +inf), decided on the bits
 __device__ inline bool bf_pos(uint16_t b) { return (int16_t)b > 0 && (b & 0x7fffu) <= 0x7f80u; }
 
-template <int MODE, int TM, int TN, bool HEAD>
+template <int MODE, int TM, int TN, int HEAD>
 __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   constexpr int ROWS = 4 * TN, SH = ROWS + 2, SW = 18, PS = 40;
   constexpr int NXV = SH * SW * 4, NXT = (NXV + 255) / 256;  // input 16-B vectors per chunk
   constexpr int NAV = TM * 9 * 64, NAT = (NAV + 255) / 256;  // weight 16-B vectors per chunk
-  constexpr int XS_TILE = SH * SW * PS, XS_HEAD = HEAD ? head_lds_elems<uint16_t, uint16_t, TM>() : 0;
+  constexpr int XS_TILE = SH * SW * PS, XS_HEAD = HEAD ? head_lds_elems<uint16_t, uint16_t, TM, HEAD>() : 0;
   __shared__ __attribute__((aligned(16))) uint16_t Xs[XS_TILE > XS_HEAD ? XS_TILE : XS_HEAD];
   __shared__ __attribute__((aligned(16))) uint16_t As[NAV * 8];
 
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   }
   if constexpr (HEAD) {
     __syncthreads();  // the head's re-layout reuses Xs
-    conv_epilogue<uint16_t, uint16_t, TM, TN, true, true>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
+    conv_epilogue<uint16_t, uint16_t, TM, TN, HEAD, true>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
   } else {
     // bf16 store of 4 channels per lane; ReLU on the rounded bits (round-to-nearest-even keeps
     // the sign, so this equals rounding max(v, 0)).  Cout % 16 == 0 and ldy % 4 == 0 (host).
@@ -746,13 +747,13 @@ __device__ inline void lds_epilogue_f32(const ConvArgs& a, f32x4 (&acc)[TM][TN],
   }
 }
 
-template <int MODE, int TM, int TN, bool HEAD>
+template <int MODE, int TM, int TN, int HEAD>
 __global__ __launch_bounds__(256, 2) void k_conv_lds_f32(ConvArgs a) {
   constexpr int KC = 16, ROWS = 4 * TN, SH = ROWS + 2, SW = 18, PS = 20;
   constexpr int NXV = SH * SW * 4, NXT = (NXV + 255) / 256;  // input 16-B vectors per chunk
   constexpr int NAV = TM * 9 * 64, NAT = (NAV + 255) / 256;  // weight 16-B vectors per chunk
   // the fused head's epilogue reuses Xs (re-layout and output staging regions)
-  constexpr int XS_TILE = SH * SW * PS, XS_HEAD = HEAD ? head_lds_elems<float, float, TM>() : 0;
+  constexpr int XS_TILE = SH * SW * PS, XS_HEAD = HEAD ? head_lds_elems<float, float, TM, HEAD>() : 0;
   __shared__ __attribute__((aligned(16))) float Xs[XS_TILE > XS_HEAD ? XS_TILE : XS_HEAD];
   __shared__ __attribute__((aligned(16))) float As[NAV * 4];
 
@@ -892,13 +893,13 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds_f32(ConvArgs a) {
   }
   if constexpr (HEAD) {
     __syncthreads();  // the head's re-layout reuses Xs
-    conv_epilogue<float, float, TM, TN, true, true>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
+    conv_epilogue<float, float, TM, TN, HEAD, true>(a, acc, ty0 + wave * TN, tx0, cob, n, lane, wave, Xs);
   } else {
     lds_epilogue_f32<TM, TN>(a, acc, ty0 + wave * TN, tx0, cob, n, lane);
   }
 }
 
-template <int MODE, bool HEAD>
+template <int MODE, int HEAD>
 void launch_conv_lds_f32_m(const ConvArgs& a, hipStream_t st) {
   ConvArgs b = a;
   b.ntx = (a.W + 15) / 16;
@@ -923,7 +924,7 @@ void launch_conv_lds_f32_m(const ConvArgs& a, hipStream_t st) {
 
 // Every fp32 3x3 convolution with more than 16 input channels (its weights are packed in
 // 16-channel chunks, which only this kernel reads).  false: 32-bit offsets would overflow.
-template <bool HEAD>
+template <int HEAD>
 bool launch_conv_lds_f32(const ConvArgs& a, hipStream_t st) {
   const size_t px = (size_t)a.N * a.H * a.W;
   const size_t ex = a.mode == APS_CONV_POOL2 ? 4 * px * a.Cx
@@ -932,14 +933,14 @@ bool launch_conv_lds_f32(const ConvArgs& a, hipStream_t st) {
   if ((ex > e2 ? ex : e2) + 16 >= ((size_t)1 << 31)) return false;
   if constexpr (HEAD) {
     if (a.mode != APS_CONV_DIRECT) return false;
-    launch_conv_lds_f32_m<APS_CONV_DIRECT, true>(a, st);
+    launch_conv_lds_f32_m<APS_CONV_DIRECT, HEAD>(a, st);
     return true;
   } else {
     switch (a.mode) {
-      case APS_CONV_DIRECT: launch_conv_lds_f32_m<APS_CONV_DIRECT, false>(a, st); return true;
-      case APS_CONV_POOL2: launch_conv_lds_f32_m<APS_CONV_POOL2, false>(a, st); return true;
-      case APS_CONV_UP2_CAT: launch_conv_lds_f32_m<APS_CONV_UP2_CAT, false>(a, st); return true;
-      case kModeReluMask: launch_conv_lds_f32_m<kModeReluMask, false>(a, st); return true;
+      case APS_CONV_DIRECT: launch_conv_lds_f32_m<APS_CONV_DIRECT, 0>(a, st); return true;
+      case APS_CONV_POOL2: launch_conv_lds_f32_m<APS_CONV_POOL2, 0>(a, st); return true;
+      case APS_CONV_UP2_CAT: launch_conv_lds_f32_m<APS_CONV_UP2_CAT, 0>(a, st); return true;
+      case kModeReluMask: launch_conv_lds_f32_m<kModeReluMask, 0>(a, st); return true;
       default: return false;
     }
   }
@@ -948,7 +949,7 @@ bool launch_conv_lds_f32(const ConvArgs& a, hipStream_t st) {
 // Launch k_conv_lds for a bf16 3x3 convolution with bf16 output whose input channels fill
 // 32-channel chunks (Cin > 16); TM = 2 for Cout <= 32, else 4 with ceil(Cout / 64) channel
 // blocks; 8-row blocks for small problems.
-template <int MODE, bool HEAD>
+template <int MODE, int HEAD>
 void launch_conv_lds_m(const ConvArgs& a, hipStream_t st) {
   ConvArgs b = a;
   b.ntx = (a.W + 15) / 16;
@@ -967,7 +968,7 @@ void launch_conv_lds_m(const ConvArgs& a, hipStream_t st) {
 }
 
 // false: the configuration is not covered (the caller uses k_conv)
-template <bool HEAD>
+template <int HEAD>
 bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
   if (a.Cout <= 16 || a.Cout % 16 || a.ldy % 4) return false;
   // the kernel addresses its inputs with 32-bit element offsets
@@ -978,14 +979,14 @@ bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
   if ((ex > e2 ? ex : e2) + kChunk >= ((size_t)1 << 31)) return false;
   if constexpr (HEAD) {
     if (a.mode != APS_CONV_DIRECT) return false;
-    launch_conv_lds_m<APS_CONV_DIRECT, true>(a, st);
+    launch_conv_lds_m<APS_CONV_DIRECT, HEAD>(a, st);
     return true;
   } else {
     switch (a.mode) {
-      case APS_CONV_DIRECT: launch_conv_lds_m<APS_CONV_DIRECT, false>(a, st); return true;
-      case APS_CONV_POOL2: launch_conv_lds_m<APS_CONV_POOL2, false>(a, st); return true;
-      case APS_CONV_UP2_CAT: launch_conv_lds_m<APS_CONV_UP2_CAT, false>(a, st); return true;
-      case kModeReluMask: launch_conv_lds_m<kModeReluMask, false>(a, st); return true;
+      case APS_CONV_DIRECT: launch_conv_lds_m<APS_CONV_DIRECT, 0>(a, st); return true;
+      case APS_CONV_POOL2: launch_conv_lds_m<APS_CONV_POOL2, 0>(a, st); return true;
+      case APS_CONV_UP2_CAT: launch_conv_lds_m<APS_CONV_UP2_CAT, 0>(a, st); return true;
+      case kModeReluMask: launch_conv_lds_m<kModeReluMask, 0>(a, st); return true;
       default: return false;
     }
   }
@@ -1223,13 +1224,14 @@ void launch_conv(const ConvArgs& a, hipStream_t st) {
   k_conv<T, TO, KS, TM, TN, CG><<<grid, 256, 0, st>>>(b);
 }
 
-// 3x3 conv (Cout = 16 TM, one block covers all of it) with its 1x1 head in the epilogue.
-template <typename T, int TM>
-void launch_conv_head(const ConvArgs& a, hipStream_t st) {
+// 3x3 conv (Cout = 16 TM, one block covers all of it) with its 1x1 head of HM m-tiles in the
+// epilogue.
+template <typename T, int TM, int HM>
+void launch_conv_head_hm(const ConvArgs& a, hipStream_t st) {
   if constexpr (sizeof(T) == 2) {
-    if (launch_conv_lds<true>(a, st)) return;
+    if (launch_conv_lds<HM>(a, st)) return;
   } else {
-    if (launch_conv_lds_f32<true>(a, st)) return;
+    if (launch_conv_lds_f32<HM>(a, st)) return;
   }
   const bool big = (size_t)a.H * a.W >= 64 * 64;
   const int TN = big ? 4 : 2, TH = 4 * TN;
@@ -1238,8 +1240,15 @@ void launch_conv_head(const ConvArgs& a, hipStream_t st) {
   b.ntiles = b.ntx * ((a.H + TH - 1) / TH);
   b.nco = 1;
   dim3 grid(xcd_grid(b.ntiles, 1), 1, a.N);
-  if (big) k_conv<T, T, 3, TM, 4, 4, true><<<grid, 256, 0, st>>>(b);
-  else k_conv<T, T, 3, TM, 2, 4, true><<<grid, 256, 0, st>>>(b);
+  if (big) k_conv<T, T, 3, TM, 4, 4, HM><<<grid, 256, 0, st>>>(b);
+  else k_conv<T, T, 3, TM, 2, 4, HM><<<grid, 256, 0, st>>>(b);
+}
+
+// heads of up to 64 logits keep the four-m-tile epilogue (fewer registers); 65..80 take five
+template <typename T, int TM>
+void launch_conv_head(const ConvArgs& a, hipStream_t st) {
+  if (a.hK > 64) launch_conv_head_hm<T, TM, 5>(a, st);
+  else launch_conv_head_hm<T, TM, 4>(a, st);
 }
 
 // ---- 1x1 convolution for the logit heads -------------------------------------------------------
@@ -1332,7 +1341,7 @@ __global__ __launch_bounds__(256) void k_conv1x1(ConvArgs a) {
 // false: not covered (the caller uses k_conv)
 template <typename T, typename TO>
 bool launch_conv1x1(const ConvArgs& a, hipStream_t st) {
-  if (a.C2 != 0 || a.Cx % 8 || a.nchunk > 8 || a.Cout > 64) return false;
+  if (a.C2 != 0 || a.Cx % 8 || a.nchunk > 8 || a.Cout > 80) return false;
   if (a.mode != APS_CONV_DIRECT && a.mode != APS_CONV_POOL2) return false;
   const size_t npix = (size_t)a.N * a.H * a.W;
   const size_t blocks = (npix + 63) / 64;
@@ -1346,7 +1355,8 @@ bool launch_conv1x1(const ConvArgs& a, hipStream_t st) {
   if (mt == 1) { APS_C1X1(1) }
   else if (mt == 2) { APS_C1X1(2) }
   else if (mt == 3) { APS_C1X1(3) }
-  else { APS_C1X1(4) }
+  else if (mt == 4) { APS_C1X1(4) }
+  else { APS_C1X1(5) }
 #undef APS_C1X1
   return true;
 }
@@ -1939,12 +1949,13 @@ int aps_conv2d_fwd_head_ex(const void* x, const void* x2, int N, int H, int W, i
     if (side_offset < 0 || side_offset + 3 > K) return APS_ERR_SHAPE;
     // the side output is written from the staged logit rows (conv_epilogue)
     const size_t es = dtype == APS_BF16 ? 2 : 4;
-    if (kstride > 64 || (kstride * es) % 16 || (reinterpret_cast<uintptr_t>(logits) & 15) ||
+    if (kstride > 16 * ((K + 15) / 16 > 4 ? 5 : 4) || (kstride * es) % 16 ||
+        (reinterpret_cast<uintptr_t>(logits) & 15) ||
         (reinterpret_cast<uintptr_t>(side) & (4 * es - 1)))
       return APS_ERR_UNSUPPORTED;
   }
   if (Cout != 32 && Cout != 64) return APS_ERR_UNSUPPORTED;
-  if (K > 64 || Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2) != 4) return APS_ERR_UNSUPPORTED;
+  if (K > 80 || Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2) != 4) return APS_ERR_UNSUPPORTED;
   if (y && ldy < Cout) return APS_ERR_SHAPE;
   if (mode == APS_CONV_UP2_CAT) {
     if (!x2 || C2 <= 0) return APS_ERR_NULL;

@@ -61,7 +61,7 @@ def test_unet_matches_oracle(ops, dtype, heads):
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-@pytest.mark.parametrize("cout,K", [(32, 34), (32, 43), (64, 34), (64, 58)])
+@pytest.mark.parametrize("cout,K", [(32, 34), (32, 43), (64, 34), (64, 58), (32, 67), (64, 67), (32, 80)])
 def test_fused_head_bit_identical(ops, dtype, cout, K):
     from paper_2602_08642_amd import _lib as L
     g = torch.Generator().manual_seed(cout * 100 + K)
@@ -202,7 +202,8 @@ def test_kernel_predict_equals_layer_chain(ops, N, H, W):
                                            (torch.bfloat16, torch.float32, 1e-2),
                                            (torch.float32, torch.float32, 1e-5)])
 @pytest.mark.parametrize("cin,cout,mode", [(32, 25, "direct"), (256, 64, "direct"), (40, 34, "direct"),
-                                           (256, 29, "pool2"), (128, 61, "pool2")])
+                                           (256, 29, "pool2"), (128, 61, "pool2"), (32, 67, "direct"),
+                                           (64, 80, "pool2")])
 def test_conv1x1_matches_oracle(ops, dtype, odt, tol, cin, cout, mode):
     """The 1x1 (logit head) convolution against the FP64 oracle: a pixel count that fills no
     whole wave (2 x 7 x 9), input channels that end inside a 32-channel chunk (40), up to 256
