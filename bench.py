@@ -99,12 +99,69 @@ def cpu_baseline(cfg, dw, kw, rows: int):
     out = of.denoise_pyramid(Ls, logits, cfg.KD, cfg.KU, cfg.KT)[0]
     dt = time.perf_counter() - t0
     assert torch.isfinite(out).all()
-    return dict(value=round(H * W / dt / 1e6, 5), unit="Mpixel/s", cores=torch.get_num_threads(),
-                kind="oracle", seconds=round(dt, 3),
-                sample=(f"one {W}x{H} band of the {cfg.W}x{cfg.H} frame" if H < cfg.H else
-                        f"one whole {W}x{H} frame") +
-                       ", full path (sampler CNN, normalisation, mask, scatter, pyramid, U-Net, "
-                       "gathering pyramid) in FP64")
+    res = dict(value=round(H * W / dt / 1e6, 5), unit="Mpixel/s", cores=torch.get_num_threads(),
+               kind="oracle", seconds=round(dt, 3),
+               sample=(f"one {W}x{H} band of the {cfg.W}x{cfg.H} frame" if H < cfg.H else
+                       f"one whole {W}x{H} frame") +
+                      ", full path (sampler CNN, normalisation, mask, scatter, pyramid, U-Net, "
+                      "gathering pyramid) in FP64")
+    return res, feat, logits
+
+
+def cpu_baseline_1core(cfg, dw, kw, rows: int):
+    """The same oracle path on one host thread, on a band of `rows` rows of the frame."""
+    import torch
+    n = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        r, _, _ = cpu_baseline(cfg, dw, kw, rows)
+    finally:
+        torch.set_num_threads(n)
+    return r
+
+
+def precision_vs_oracle(cfg, kw, feat, logits_ref, dev):
+    """Per-head error of the library's U-Net against the FP64 oracle on the oracle frame's
+    features: in the configuration's dtype (against logits_ref), and the same network in bf16
+    (against the oracle on the bf16-rounded weights and features).  Per head: the normwise
+    relative error and the largest abs(y - r) / (abs(r) + rms(r))."""
+    import numpy as np
+    import torch
+
+    from oracle import unet as ou
+    from paper_2602_08642_amd import ops, pipeline
+
+    kspec = pipeline.kernel_spec(cfg)
+    heads = cfg.head_channels()
+
+    def errs(got, ref):
+        out = []
+        for l, K in enumerate(heads):
+            y = got[l][..., :K].double().cpu().numpy()
+            r = ref[l].numpy()
+            rms = float(np.sqrt(np.mean(r * r)))
+            out.append({"head": l, "K": K,
+                        "normwise": float(f"{np.linalg.norm(y - r) / np.linalg.norm(r):.3e}"),
+                        "max_elem": float(f"{np.max(np.abs(y - r) / (np.abs(r) + rms)):.3e}")})
+        return out
+
+    res = {"what": "U-Net logits of the oracle frame's features; per head: normwise relative error and "
+                   "max abs(y - r) / (abs(r) + rms(r))"}
+    for dt in (cfg.net_dtype, torch.bfloat16):
+        key = "fp32" if dt == torch.float32 else "bf16"
+        if key in res:
+            continue
+        net = ops.Net(kspec, kw, dt, dev)
+        x = feat.to(dt)
+        got = ops.kernel_predict(net, x.float().to(dev).to(dt), heads, dt)
+        if dt == cfg.net_dtype and dt == torch.float32:
+            ref = logits_ref
+        else:
+            wq = {k: (torch.tensor(a).to(dt).double(), torch.tensor(b).double()) for k, (a, b) in kw.items()}
+            ref = ou.unet_forward(x.double(), wq, len(heads))
+        res[key] = errs(got, ref)
+        del net, got
+    return res
 
 
 def bench_config(name, steps, warmup, dev, seed=2602):
@@ -222,6 +279,41 @@ def bench_config(name, steps, warmup, dev, seed=2602):
                   + (", recurrent latents" if cfg.latents else "")))
 
 
+def bench_train(dev, steps=3, warmup=1):
+    """One C4 training step (batch of 4 clips of 8 frames at 256x256, 0.25 spp budget range,
+    bf16 networks with fp32 masters): every frame forward and backward through both networks,
+    the relaxed sampling step, the filter and the loss, then AdamW.  The clips are generated
+    before timing.  FLOPs: the U-Net and sampler forward per frame times 3 (forward, data
+    gradient and weight gradient), the forward recomputation inside the filter backward not
+    counted."""
+    import torch
+
+    from paper_2602_08642_amd import pipeline, train
+    cfg = pipeline.CONFIGS["c4"]
+    tc = train.TrainConfig(steps=warmup + steps, batch=4, frames=8, n_train_clips=4)
+    tr = train.Trainer(cfg, tc, dev)
+    tr.clips(0)
+    for _ in range(warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    dspec, kspec = pipeline.density_spec(cfg), pipeline.kernel_spec(cfg)
+    px = cfg.H * cfg.W
+    fwd = unet_flops(cfg, kspec) + sum(2 * l["k"] * l["k"] * l["cin"] * l["cout"] * px for l in dspec)
+    flops = 3 * fwd * tc.batch * tc.frames
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"workload": f"c4: {tc.batch} clips x {tc.frames} frames of {cfg.W}x{cfg.H}, bf16 networks, "
+                        "relaxed sampling step, window-2 truncated back-propagation, AdamW",
+            "ms_per_step": round(ms, 2), "steps": steps, "warmup": warmup,
+            "mfma": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["bf16_mfma_TFLOPs"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["bf16_mfma_TFLOPs"], 4),
+                     "flop_per_step": flops}}
+
+
 WEIGHTS = os.path.join(ROOT, "paper_2602_08642_amd", "weights", "c4_trained.npz")
 CSRC = os.path.join(ROOT, "paper_2602_08642_amd", "csrc")
 TRAFFIC_SOURCES = ("aps_common.h", "conv.hip", "net.hip")
@@ -255,35 +347,14 @@ def measured_traffic(config):
     return int(fields["traffic_bytes_per_frame"])
 
 
-def quality(dev, seeds=(10000, 10001, 10002, 10003), frames=8):
-    """Learned vs uniform vs fallback error on held-out procedural clips with the trained
-    weights (256x256, 0.25 spp), and the uniform budget that matches the learned error."""
-    from paper_2602_08642_amd import evaluate, pipeline, train
+def quality(dev):
+    """Learned vs uniform vs fallback error of the trained C4 weights on 16 held-out procedural
+    clips (256x256, 8 frames, 0.25 spp): the paired per-clip PSNR gain with its 95 % interval,
+    and the uniform budget that matches the learned error."""
+    from paper_2602_08642_amd import evaluate
     if not os.path.exists(WEIGHTS):
         return None
-    w = evaluate.load_weights(WEIGHTS)
-    cfg = pipeline.CONFIGS["c4"]
-    dnet = train.TrainNet(pipeline.density_spec(cfg), w["density"], cfg.net_dtype, dev)
-    kl = train.TrainNet(pipeline.kernel_spec(cfg), w["kernel_learned"], cfg.net_dtype, dev)
-    ku = train.TrainNet(pipeline.kernel_spec(cfg), w["kernel_uniform"], cfg.net_dtype, dev)
-    seeds = list(seeds)
-    res = {"workload": "held-out procedural 256x256 clips x 8 frames, 0.25 spp, hard mask",
-           "learned": train.evaluate(cfg, dnet, kl, seeds, frames, dev),
-           "uniform": train.evaluate(cfg, None, ku, seeds, frames, dev, uniform=True),
-           "fallback": train.evaluate(cfg, None, None, seeds, frames, dev, uniform=True)}
-    sweep = [train.evaluate(cfg, None, ku, seeds, frames, dev, uniform=True, budget=b)
-             for b in (0.25, 0.3, 0.35, 0.4, 0.5, 0.6, 0.75, 1.0)]
-    tgt = res["learned"]["psnr"]
-    eq = None
-    for a, b in zip(sweep[:-1], sweep[1:]):
-        if a["psnr"] <= tgt <= b["psnr"] and b["psnr"] > a["psnr"]:
-            eq = a["budget"] + (tgt - a["psnr"]) / (b["psnr"] - a["psnr"]) * (b["budget"] - a["budget"])
-            break
-    res["uniform_budget_sweep_psnr"] = {str(s["budget"]): round(s["psnr"], 3) for s in sweep}
-    res["equal_error_uniform_spp"] = None if eq is None else round(eq, 4)
-    res["equal_error_sample_ratio"] = None if eq is None else round(eq / cfg.budget, 3)
-    res["psnr_gain_db_vs_uniform"] = round(res["learned"]["psnr"] - res["uniform"]["psnr"], 3)
-    return res
+    return evaluate.compare_trained(WEIGHTS, device=dev)
 
 
 def main():
@@ -297,6 +368,8 @@ def main():
                     help="rows of the frame the CPU oracle processes (0: the whole frame)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--no-train", action="store_true", help="skip the C4 training-step timing")
+    ap.add_argument("--only-train", action="store_true", help="only the C4 training-step timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales the HBM "
                          "traffic counters FETCH_SIZE / WRITE_SIZE of a profiled run)")
@@ -320,6 +393,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only_train:
+        print(json.dumps({"training_step": bench_train(dev, steps=args.steps, warmup=args.warmup)}))
+        return
     r = bench_config(args.config, args.steps, args.warmup, dev)
     cfg = r["cfg"]
     res = {
@@ -354,12 +430,19 @@ def main():
         torch.cuda.empty_cache()
     if also:
         res["also_timed"] = also
+    if not args.no_train:
+        res["training_step"] = bench_train(dev)
+        torch.cuda.empty_cache()
     if not args.no_quality:
         q = quality(dev)
         if q is not None:
             res["learned_vs_uniform"] = q
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(cfg, r["dw"], r["kw"], args.cpu_rows or cfg.H)
+        cb, feat, logits = cpu_baseline(cfg, r["dw"], r["kw"], args.cpu_rows or cfg.H)
+        # one thread on a band of about an eighth of the rows (a multiple of 8 for the U-Net)
+        cb["one_core"] = cpu_baseline_1core(cfg, r["dw"], r["kw"], max(8, (args.cpu_rows or cfg.H) // 64 * 8))
+        res["cpu_baseline"] = cb
+        res["precision_vs_fp64"] = precision_vs_oracle(cfg, r["kw"], feat, logits, dev)
     print(json.dumps(res))
 
 

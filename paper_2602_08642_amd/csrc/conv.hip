@@ -1566,36 +1566,73 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
   const int ci = (int)(i % Cin);
   const int tap = (int)((i / Cin) % KK);
   const int co = (int)(i / ((size_t)Cin * KK));
-  float s = 0.f;
-  for (int k = 0; k < splits; ++k) s += part[(((size_t)k * CoutP + co) * KK + tap) * CinP + ci];
-  dw[i] = s;
+  // four accumulators over the splits k = j mod 4 (independent loads in flight), fixed order
+  const size_t stride = (size_t)CoutP * KK * CinP;
+  const float* pp = part + ((size_t)co * KK + tap) * CinP + ci;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int k = 0;
+  for (; k + 3 < splits; k += 4) {
+    s0 += pp[(size_t)k * stride];
+    s1 += pp[(size_t)(k + 1) * stride];
+    s2 += pp[(size_t)(k + 2) * stride];
+    s3 += pp[(size_t)(k + 3) * stride];
+  }
+  for (; k < splits; ++k) s0 += pp[(size_t)k * stride];
+  dw[i] = (s0 + s1) + (s2 + s3);
 }
 
-// db[co] = sum_px dY[px][co] (masked): per-block partials, then a fixed-order sum
+// db[co] = sum_px dY[px][co] (masked), deterministic: block b sums the pixels [b per, (b+1) per).
+// Thread t takes channel co = t % Cout and pixel lane r = t / Cout (R = 256 / Cout lanes): pixels
+// p0 + r, p0 + r + R, ... in order into four accumulators (independent loads in flight), then the
+// lanes of a channel are added in lane order.  The second pass sums the block partials of one
+// channel per block: a fixed stride per thread, then a fixed pairwise tree.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bias_partial(const T* __restrict__ dy,
                                                       const T* __restrict__ ym, int ldy, int Cout,
                                                       size_t npix, size_t per,
                                                       float* __restrict__ part) {
-  const int co = threadIdx.x;
-  if (co >= Cout) return;
-  const size_t p0 = (size_t)blockIdx.x * per, p1 = min(npix, p0 + per);
-  float s = 0.f;
-  for (size_t p = p0; p < p1; ++p) {
-    float g = Ld<T>::get(dy, p * ldy + co);
-    if (ym && !(Ld<T>::get(ym, p * Cout + co) > 0.f)) g = 0.f;
-    s += g;
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  const int R = 256 / Cout;  // Cout <= 256
+  const int co = t % Cout, r = t / Cout;
+  auto g = [&](size_t p) {
+    const float v = Ld<T>::get(dy, p * ldy + co);
+    return ym && !(Ld<T>::get(ym, p * Cout + co) > 0.f) ? 0.f : v;
+  };
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  if (r < R) {
+    const size_t p0 = (size_t)blockIdx.x * per, p1 = min(npix, p0 + per);
+    size_t p = p0 + r;
+    for (; p + 3 * (size_t)R < p1; p += 4 * (size_t)R) {
+      s0 += g(p);
+      s1 += g(p + R);
+      s2 += g(p + 2 * R);
+      s3 += g(p + 3 * R);
+    }
+    for (; p < p1; p += R) s0 += g(p);
   }
-  part[(size_t)blockIdx.x * Cout + co] = s;
+  red[t] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (r == 0) {
+    float a = 0.f;
+    for (int k = 0; k < R; ++k) a += red[k * Cout + co];
+    part[(size_t)blockIdx.x * Cout + co] = a;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_bias_reduce(const float* __restrict__ part, int nb,
                                                      int Cout, float* __restrict__ db) {
-  const int co = blockIdx.x * 256 + threadIdx.x;
-  if (co >= Cout) return;
+  __shared__ float red[256];
+  const int co = blockIdx.x, t = threadIdx.x;
   float s = 0.f;
-  for (int b = 0; b < nb; ++b) s += part[(size_t)b * Cout + co];
-  db[co] = s;
+  for (int b = t; b < nb; b += 256) s += part[(size_t)b * Cout + co];
+  red[t] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) db[co] = red[0];
 }
 
 struct WgradPlan {
@@ -1612,7 +1649,8 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int KS) {
   p.CoutP = (Cout + 31) / 32 * 32;
   p.CinP = p.nchunk * kChunk;
   const int tiles = (p.CoutP / 32) * p.nchunk;
-  int want = (1024 + tiles - 1) / tiles;
+  // about 512 workgroups: enough to fill the chip, few partial sums to write and reduce
+  int want = (512 + tiles - 1) / tiles;
   if (want > 256) want = 256;
   if (want < 1) want = 1;
   if (want > p.nblocks) want = p.nblocks;
@@ -1620,7 +1658,7 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int KS) {
   p.splits = (p.nblocks + p.bps - 1) / p.bps;
   p.part_bytes = (size_t)p.splits * p.CoutP * KS * KS * p.CinP * sizeof(float);
   const size_t npix = (size_t)N * H * W;
-  p.bias_per = 1024;
+  p.bias_per = (size_t)16 * (256 / (Cout < 256 ? Cout : 256));  // 16 pixels per lane
   p.bias_blocks = (npix + p.bias_per - 1) / p.bias_per;
   return p;
 }
@@ -1876,7 +1914,7 @@ int aps_conv2d_bwd_weight(const void* x, const void* x2, int mode, int N, int H,
       k_bias_partial<uint16_t><<<(unsigned)p.bias_blocks, 256, 0, st>>>(
           static_cast<const uint16_t*>(dy), static_cast<const uint16_t*>(ymask), ldy, Cout, npix,
           p.bias_per, bpart);
-    k_bias_reduce<<<(Cout + 255) / 256, 256, 0, st>>>(bpart, (int)p.bias_blocks, Cout, db);
+    k_bias_reduce<<<Cout, 256, 0, st>>>(bpart, (int)p.bias_blocks, Cout, db);
   }
   APS_LAUNCH_CHECK();
   return APS_OK;

@@ -46,6 +46,62 @@ def load_weights(path):
     return out
 
 
+# held-out scene seeds (training uses seeds 0..1023)
+HELD_OUT = tuple(range(10000, 10016))
+
+
+def paired_gain(a, b):
+    """Paired per-clip PSNR differences a - b (same clips, same sample pools): mean, standard
+    deviation, two-sided 95 % Student-t interval of the mean, and the clips where a is better."""
+    from scipy import stats
+    d = np.asarray(a["psnr_per_clip"], np.float64) - np.asarray(b["psnr_per_clip"], np.float64)
+    n = d.size
+    m, sd = float(d.mean()), float(d.std(ddof=1))
+    h = float(stats.t.ppf(0.975, n - 1)) * sd / np.sqrt(n)
+    return {"clips": int(n), "mean_db": round(m, 4), "sd_db": round(sd, 4),
+            "ci95_db": [round(m - h, 4), round(m + h, 4)], "clips_better": int((d > 0).sum())}
+
+
+def equal_error_budget(target_psnr, sweep):
+    """Uniform budget whose PSNR equals target_psnr (linear interpolation of PSNR over the
+    budget sweep), or None outside the sweep."""
+    for a, b in zip(sweep[:-1], sweep[1:]):
+        if a["psnr"] <= target_psnr <= b["psnr"] and b["psnr"] > a["psnr"]:
+            return a["budget"] + (target_psnr - a["psnr"]) / (b["psnr"] - a["psnr"]) * (b["budget"] - a["budget"])
+    return None
+
+
+def compare_trained(weights_path, seeds=HELD_OUT, frames=8, device="cuda",
+                    budgets=(0.25, 0.3, 0.35, 0.4, 0.5, 0.6, 0.75, 1.0)):
+    """The shipped C4 weights on held-out clips at 0.25 spp: learned (sampler + kernels), uniform
+    sampling with its own kernels ("Ours Uniform", Sec. 7) and the fixed-kernel fallback; the
+    paired learned - uniform PSNR gain with its 95 % interval, and the uniform budget of equal
+    error."""
+    w = load_weights(weights_path)
+    cfg = pipeline.CONFIGS["c4"]
+    dnet = train.TrainNet(pipeline.density_spec(cfg), w["density"], cfg.net_dtype, device)
+    kl = train.TrainNet(pipeline.kernel_spec(cfg), w["kernel_learned"], cfg.net_dtype, device)
+    ku = train.TrainNet(pipeline.kernel_spec(cfg), w["kernel_uniform"], cfg.net_dtype, device)
+    seeds = list(seeds)
+    res = {"workload": f"held-out procedural {cfg.W}x{cfg.H} clips (scene seeds {seeds[0]}-{seeds[-1]}) x "
+                       f"{frames} frames, {cfg.budget} spp, hard mask",
+           "learned": train.evaluate(cfg, dnet, kl, seeds, frames, device),
+           "uniform": train.evaluate(cfg, None, ku, seeds, frames, device, uniform=True),
+           "fallback": train.evaluate(cfg, None, None, seeds, frames, device, uniform=True)}
+    sweep = [res["uniform"]] + [train.evaluate(cfg, None, ku, seeds, frames, device, uniform=True, budget=b)
+                                for b in budgets if b != cfg.budget]
+    eq = equal_error_budget(res["learned"]["psnr"], sweep)
+    res["paired_gain_vs_uniform"] = paired_gain(res["learned"], res["uniform"])
+    res["paired_gain_vs_fallback"] = paired_gain(res["learned"], res["fallback"])
+    res["uniform_budget_sweep_psnr"] = {str(e["budget"]): round(e["psnr"], 3) for e in sweep}
+    res["equal_error_uniform_spp"] = None if eq is None else round(eq, 4)
+    res["equal_error_sample_ratio"] = None if eq is None else round(eq / cfg.budget, 3)
+    for k in ("learned", "uniform", "fallback"):
+        res[k] = {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in res[k].items()
+                  if kk != "psnr_per_clip"}
+    return res
+
+
 def run(steps=300, batch=4, frames=8, lr=1e-3, eval_seeds=tuple(range(10000, 10008)),
         budgets=(0.25, 0.3, 0.35, 0.4, 0.5, 0.6, 0.75, 1.0), device="cuda", cfg_name="c4", log=print,
         H=None):

@@ -651,9 +651,11 @@ def adamw_step(param, m, v, grad, lr, step, beta1=0.8, beta2=0.985, eps=1e-8, we
             "adamw_step")
 
 
-def sumsq(x):
+def sumsq(x, out=None):
+    """Sum of squares of x into a device scalar (out: an existing 1-element float32 slot)."""
     _need(x, "x", _F32)
-    out = torch.empty(1, dtype=_F32, device=x.device)
+    if out is None:
+        out = torch.empty(1, dtype=_F32, device=x.device)
     lib = L.load()
     nb = lib.aps_sumsq_workspace_size(x.numel())
     ws = WS.get(nb, x.device)

@@ -214,86 +214,142 @@ def cosine_lr(step, total, peak):
     return 0.5 * peak * (1.0 + math.cos(math.pi * min(step, total) / max(total, 1)))
 
 
-def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, kw=None):
-    import procgen
-    dspec, kspec = density_spec(cfg), kernel_spec(cfg)
-    dw = dw or procgen.init_weights(dspec, 7)
-    if kw is None:
-        kw = procgen.init_weights(kspec, 8)
-        if cfg.demod or cfg.latents:
-            # the demodulation map and the latents start at zero (d = 1: the plain path), so
-            # training departs from the path without them instead of from a random map
-            hname = kspec[-1]["name"] if cfg.kernel_net == "cnn3" else "head0"
-            k0 = cfg.filter_channels()[0]
-            w, b = kw[hname]
-            w, b = w.copy(), b.copy()
-            w[k0:] = 0.0
-            b[k0:] = 0.0
-            kw = dict(kw)
-            kw[hname] = (w, b)
-    dnet = None if tc.uniform else TrainNet(dspec, dw, cfg.net_dtype, device)
-    knet = TrainNet(kspec, kw, cfg.net_dtype, device)
-    nets = [knet] + ([] if dnet is None else [dnet])
-    pool_clips = [list(range(c * tc.batch, (c + 1) * tc.batch)) for c in range(tc.n_train_clips // tc.batch)]
-    data = {}
-    gen = torch.Generator(device=device).manual_seed(tc.seed)
-    history = []
-    t0 = time.time()
-    for step in range(1, tc.steps + 1):
-        ci = (step - 1) % len(pool_clips)
-        if ci not in data:
-            data[ci] = make_clips(pool_clips[ci], cfg.H, cfg.W, tc.frames, device, rng_seed=ci)
-        cb = data[ci]
+class Trainer:
+    """The training loop's state (networks, AdamW moments, step count, clip cache) and one step.
+
+    A step trains on one batch of clips: every frame forward and backward through the library's
+    kernels (window-2 truncated back-propagation through the temporal loop), then AdamW on the
+    fp32 masters with the gradients averaged over the frames.  The gradient-norm guard reduces
+    every parameter's sum of squares into one device vector that is read back once per step,
+    together with the frame losses; a step with a non-finite norm is skipped."""
+
+    def __init__(self, cfg: FrameConfig, tc: TrainConfig, device="cuda", dw=None, kw=None):
+        import procgen
+        self.cfg, self.tc, self.device = cfg, tc, device
+        dspec, kspec = density_spec(cfg), kernel_spec(cfg)
+        dw = dw or procgen.init_weights(dspec, 7)
+        if kw is None:
+            kw = procgen.init_weights(kspec, 8)
+            if cfg.demod or cfg.latents:
+                # the demodulation map and the latents start at zero (d = 1: the plain path), so
+                # training departs from the path without them instead of from a random map
+                hname = kspec[-1]["name"] if cfg.kernel_net == "cnn3" else "head0"
+                k0 = cfg.filter_channels()[0]
+                w, b = kw[hname]
+                w, b = w.copy(), b.copy()
+                w[k0:] = 0.0
+                b[k0:] = 0.0
+                kw = dict(kw)
+                kw[hname] = (w, b)
+        self.dnet = None if tc.uniform else TrainNet(dspec, dw, cfg.net_dtype, device)
+        self.knet = TrainNet(kspec, kw, cfg.net_dtype, device)
+        self.nets = [self.knet] + ([] if self.dnet is None else [self.dnet])
+        self.params = [(p, mv) for net in self.nets for _, p, mv in net.params()]
+        self.pool_clips = [list(range(c * tc.batch, (c + 1) * tc.batch))
+                           for c in range(tc.n_train_clips // tc.batch)]
+        self.data = {}
+        self.gen = torch.Generator(device=device).manual_seed(tc.seed)
+        self.step_no = 0
+        self.history = []
+
+    def clips(self, ci):
+        if ci not in self.data:
+            self.data[ci] = make_clips(self.pool_clips[ci], self.cfg.H, self.cfg.W, self.tc.frames,
+                                       self.device, rng_seed=ci)
+        return self.data[ci]
+
+    def step(self):
+        cfg, tc = self.cfg, self.tc
+        self.step_no += 1
+        step = self.step_no
+        cb = self.clips((step - 1) % len(self.pool_clips))
         prev, prev_h, prev_lat, prev_ref, gate = None, None, None, None, None
         losses = []
         lo, hi = tc.budget_range
         bstep = float(math.exp(np.random.default_rng([tc.seed, step]).uniform(math.log(lo), math.log(hi))))
         cfg_s = dataclasses.replace(cfg, budget=bstep)
         for t in range(tc.frames):
-            pool = sample_pool(cb.ref[t], gen)
+            pool = sample_pool(cb.ref[t], self.gen)
             pin = None if prev is None else _Gate.apply(prev, gate)
             hin = None if prev_h is None else (pin if prev_h is prev else _Gate.apply(prev_h, gate))
             lin = None if prev_lat is None else _Gate.apply(prev_lat, gate)
             mv = cb.mv[t] if prev is not None else None
             seed = 1_000_003 * step + t
-            out, s, out_h, lat = frame_forward(dnet, knet, cfg_s, cb.aux[t], pin, mv, pool, seed, t,
-                                               "relaxed" if tc.uniform else tc.estimator,
+            out, s, out_h, lat = frame_forward(self.dnet, self.knet, cfg_s, cb.aux[t], pin, mv, pool, seed,
+                                               t, "relaxed" if tc.uniform else tc.estimator,
                                                uniform=tc.uniform, history=hin, want_history=True,
                                                tau=tc.tau, ref=cb.ref[t], lat=lin, want_latent=True)
             loss = ag.TMOLoss.apply(out, pin, cb.ref[t], prev_ref, mv, cb.params)
             loss.backward(retain_graph=True)
             if gate is not None:
                 gate["open"] = False        # frame t-2 stays out of later windows
-            losses.append(loss.detach())
+            losses.append(loss.detach().reshape(1))
             prev, prev_h, prev_lat, prev_ref, gate = out, out_h, lat, cb.ref[t], {"open": True}
         del prev, prev_h, prev_lat, out, out_h, lat, loss, pin
-        # AdamW on the fp32 masters (gradients averaged over the frames)
+        # gradient-norm guard: every parameter's sum of squares into one device vector, read back
+        # once with the frame losses
+        sq = torch.zeros(len(self.params), dtype=F32, device=self.device)
+        for i, (p, _) in enumerate(self.params):
+            if p.grad is not None:
+                ops.sumsq(p.grad, out=sq[i:i + 1])
+        host = torch.cat(losses + [sq]).cpu().numpy().astype(np.float64)
+        lval, gn = float(host[:len(losses)].mean()), float(host[len(losses):].sum())
+        finite = math.isfinite(gn)
         lr = cosine_lr(step - 1, tc.steps, tc.lr)
-        gn = 0.0
-        finite = True
-        for net in nets:
-            for _, p, (m, v) in net.params():
-                if p.grad is None:
-                    continue
-                ss = float(ops.sumsq(p.grad).item())
-                finite &= math.isfinite(ss)
-                gn += ss
         if finite:
-            for net in nets:
-                for _, p, (m, v) in net.params():
-                    if p.grad is not None:
-                        ops.adamw_step(p.data, m, v, p.grad, lr, step, grad_scale=1.0 / tc.frames)
+            for p, (m, v) in self.params:
+                if p.grad is not None:
+                    ops.adamw_step(p.data, m, v, p.grad, lr, step, grad_scale=1.0 / tc.frames)
+            for net in self.nets:
                 net.refresh()
-        for net in nets:
-            for _, p, _ in net.params():
-                p.grad = None
-        lval = float(torch.stack(losses).mean().item())
-        history.append(dict(step=step, loss=lval, grad_norm=math.sqrt(gn), lr=lr, budget=bstep,
-                            skipped=not finite))
+        for p, _ in self.params:
+            p.grad = None
+        rec = dict(step=step, loss=lval, grad_norm=math.sqrt(gn) if finite else float("nan"), lr=lr,
+                   budget=bstep, skipped=not finite)
+        self.history.append(rec)
+        return rec
+
+    # ---- checkpoint / resume: masters, AdamW moments and the step count (the clip cache and
+    # the per-step budgets and seeds are functions of the step and the configuration)
+    def state_dict(self):
+        out = {"step": np.array(self.step_no), "gen": self.gen.get_state().numpy()}
+        for tag, net in (("k", self.knet), ("d", self.dnet)):
+            if net is None:
+                continue
+            for name, lr in net.layers.items():
+                (mw, vw), (mb, vb) = net.state[name]
+                for key, t in (("w", lr.w), ("b", lr.b), ("mw", mw), ("vw", vw), ("mb", mb), ("vb", vb)):
+                    out[f"{tag}/{name}/{key}"] = t.detach().cpu().numpy()
+        return out
+
+    def save(self, path):
+        np.savez(path, **self.state_dict())
+
+    def load(self, path):
+        z = np.load(path)
+        self.step_no = int(z["step"])
+        self.gen.set_state(torch.tensor(z["gen"]))
+        for tag, net in (("k", self.knet), ("d", self.dnet)):
+            if net is None:
+                continue
+            for name, lr in net.layers.items():
+                (mw, vw), (mb, vb) = net.state[name]
+                with torch.no_grad():
+                    for key, t in (("w", lr.w), ("b", lr.b), ("mw", mw), ("vw", vw), ("mb", mb), ("vb", vb)):
+                        t.copy_(torch.tensor(z[f"{tag}/{name}/{key}"]))
+            net.refresh()
+
+
+def train(cfg: FrameConfig, tc: TrainConfig, device="cuda", log=print, dw=None, kw=None):
+    tr = Trainer(cfg, tc, device, dw, kw)
+    t0 = time.time()
+    for _ in range(tc.steps):
+        rec = tr.step()
+        step = rec["step"]
         if step % tc.log_every == 0 or step == 1:
-            log(f"step {step:4d} loss {lval:.5f} |g| {math.sqrt(gn):.3e} lr {lr:.2e} "
+            log(f"step {step:4d} loss {rec['loss']:.5f} |g| {rec['grad_norm']:.3e} lr {rec['lr']:.2e} "
                 f"{time.time() - t0:.1f}s")
-    return dnet, knet, history
+    return tr.dnet, tr.knet, tr.history
 
 
 # ------------------------------------------------------------------ evaluation
@@ -312,14 +368,15 @@ def psnr_tonemapped(out, ref, params):
         return torch.where(t <= 0.0031308, 12.92 * t, 1.055 * torch.pow(torch.clamp(t, min=0.0031308), 1 / 2.4) - 0.055)
 
     mse = ((tm(out) - tm(ref)) ** 2).mean(dim=(1, 2, 3))
-    return (10 * torch.log10(1.0 / mse)).mean().item()
+    return (10 * torch.log10(1.0 / mse)).cpu().numpy()
 
 
 @torch.no_grad()
 def evaluate(cfg: FrameConfig, dnet, knet, seeds, frames=8, device="cuda", uniform=False,
              budget=None, gen_seed=123, mode="hard"):
     """Mean tonemapped PSNR and relMSE over held-out clips, hard mask (test time; mode "dasr":
-    deterministic rounding, the test-time forward of a DASR-trained sampler)."""
+    deterministic rounding, the test-time forward of a DASR-trained sampler); psnr_per_clip:
+    each clip's PSNR averaged over its frames, in the order of seeds."""
     if budget is not None:
         cfg = dataclasses.replace(cfg, budget=budget)
     cb = make_clips(seeds, cfg.H, cfg.W, frames, device, randomise_tmo=False)
@@ -336,4 +393,6 @@ def evaluate(cfg: FrameConfig, dnet, knet, seeds, frames=8, device="cuda", unifo
         ps.append(psnr_tonemapped(out, cb.ref[t], cb.params))
         r = cb.ref[t][..., :3]
         rm.append((((out[..., :3] - r) ** 2) / (r ** 2 + 1e-2)).mean().item())
-    return dict(psnr=float(np.mean(ps)), relmse=float(np.mean(rm)), budget=cfg.budget)
+    per_clip = np.mean(np.stack(ps), axis=0)
+    return dict(psnr=float(per_clip.mean()), relmse=float(np.mean(rm)), budget=cfg.budget,
+                psnr_per_clip=[float(v) for v in per_clip])

@@ -1,6 +1,7 @@
 """End-to-end gradients of one frame (both networks) against the FP64 oracle, and a short
 training run on procedural clips."""
 import dataclasses
+import os
 
 import numpy as np
 import pytest
@@ -150,3 +151,32 @@ def test_training_steps_with_demodulation_and_latents():
         assert torch.isfinite(lr.w).all(), name
     ev = train.evaluate(cfg, dnet, knet, [10000], 3, DEV)
     assert np.isfinite(ev["psnr"])
+
+
+def test_checkpoint_resume_continues_the_run():
+    """Trainer.save / load keep the masters, the AdamW moments, the step count and the sample
+    generator: the loaded state equals the saved one bit for bit, and the resumed run's next step
+    has the uninterrupted run's budget and loss (up to the float atomics of the warp transposes,
+    whose summation order is not fixed)."""
+    import tempfile
+
+    from paper_2602_08642_amd import pipeline, train
+    cfg = dataclasses.replace(pipeline.CONFIGS["c4"], H=64, W=64)
+    tc = train.TrainConfig(steps=4, batch=2, frames=2, n_train_clips=2, log_every=100)
+    a = train.Trainer(cfg, tc, DEV)
+    a.step()
+    a.step()
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ckpt.npz")
+        a.save(path)
+        saved = a.state_dict()
+        ra = a.step()
+        b = train.Trainer(cfg, tc, DEV)
+        b.load(path)
+        loaded = b.state_dict()
+        assert sorted(loaded) == sorted(saved)
+        for k in saved:
+            assert np.array_equal(loaded[k], saved[k]), k
+        rb = b.step()
+    assert rb["step"] == ra["step"] == 3 and rb["budget"] == ra["budget"]
+    assert abs(rb["loss"] - ra["loss"]) <= 1e-4 * abs(ra["loss"])
