@@ -496,11 +496,15 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   // element offsets at chunk 0 are computed once (32-bit; kNoPixel outside the image):
   // xo into x (for POOL2 the top-left of the 2x2 window, for UP2_CAT the parent pixel of the
   // coarse tensor), so into the skip tensor x2 (UP2_CAT only).
-  const int g8 = (tid & 3) * 8;
+  // Lane l of wave w stages pixel 16 w + l % 16 (+ 64 k) and channel group l / 16: a 16-lane
+  // group writes 16 consecutive tile pixels at the padded pixel stride, which hits distinct LDS
+  // banks (four lanes per pixel at one stride would collide every fourth pixel).
+  const int g8 = ((tid >> 4) & 3) * 8;
+  const int pl = (tid >> 6) * 16 + (tid & 15);
   uint32_t xo[NXT], so[MODE == APS_CONV_UP2_CAT ? NXT : 1];
 #pragma unroll
   for (int k = 0; k < NXT; ++k) {
-    const int p = (tid >> 2) + 64 * k, r = p / SW, col = p - r * SW;
+    const int p = pl + 64 * k, r = p / SW, col = p - r * SW;
     const int iy = ty0 - 1 + r, ix = tx0 - 1 + col;
     const bool in = p < SH * SW && iy >= 0 && iy < a.H && ix >= 0 && ix < a.W;
     uint32_t o = kNoPixel;
@@ -572,7 +576,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds(ConvArgs a) {
   auto put = [&]() {
 #pragma unroll
     for (int k = 0; k < NXT; ++k) {
-      const int p = (tid >> 2) + 64 * k;
+      const int p = pl + 64 * k;
       if (p < SH * SW) {
         const u16x8 v = (okbits >> k) & 1u ? px[k] : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
         *reinterpret_cast<u16x8*>(Xs + p * PS + g8) = v;
@@ -766,13 +770,14 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds_f32(ConvArgs a) {
   const float* x2 = static_cast<const float*>(a.x2);
   const float* wp = static_cast<const float*>(a.wp);
   const int Cin = a.Cx + a.C2;
-  // This thread stages channel group g (4 channels) of tile pixels (tid / 4) + 64 k (offsets as
-  // in k_conv_lds, in floats).
-  const int g4 = (tid & 3) * 4;
+  // This thread stages channel group g (4 channels) of tile pixel 16 w + l % 16 + 64 k, g = l / 16
+  // (lane l of wave w; bank-conflict-free writes as in k_conv_lds; offsets in floats).
+  const int g4 = ((tid >> 4) & 3) * 4;
+  const int pl = (tid >> 6) * 16 + (tid & 15);
   uint32_t xo[NXT], so[MODE == APS_CONV_UP2_CAT ? NXT : 1];
 #pragma unroll
   for (int k = 0; k < NXT; ++k) {
-    const int p = (tid >> 2) + 64 * k, r = p / SW, col = p - r * SW;
+    const int p = pl + 64 * k, r = p / SW, col = p - r * SW;
     const int iy = ty0 - 1 + r, ix = tx0 - 1 + col;
     const bool in = p < SH * SW && iy >= 0 && iy < a.H && ix >= 0 && ix < a.W;
     uint32_t o = kNoPixel;
@@ -835,7 +840,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds_f32(ConvArgs a) {
   auto put = [&]() {
 #pragma unroll
     for (int k = 0; k < NXT; ++k) {
-      const int p = (tid >> 2) + 64 * k;
+      const int p = pl + 64 * k;
       if (p < SH * SW) *reinterpret_cast<f32x4*>(Xs + p * PS + g4) = (okbits >> k) & 1u ? px[k] : zero4;
     }
 #pragma unroll
@@ -1197,16 +1202,21 @@ bool fp32_offsets_fit(int mode, int N, int H, int W, int Cx, int C2) {
   return (ex > e2 ? ex : e2) + 16 < ((size_t)1 << 31);
 }
 
-// 8-channel groups of the K layout (see k_conv): merged taps only for 3x3 with <= 16 channels
-int conv_cg(int KS, int Cin) {
+// 8-channel groups of the K layout (see k_conv).  4: 32-channel chunks (fp32: the 16-channel
+// chunks of k_conv_lds_f32), for 1x1 convolutions, 3x3 with more than 16 input channels, and
+// 3x3 with 9..16 input channels whose output channels fill whole 16-channel tiles beyond 16 (the
+// U-Net's first layer: it runs in the LDS kernels, in bf16 as one half-filled chunk).  1 or 2:
+// merged (tap, group) pairs for the other 3x3 layers with <= 16 input channels (the sampler).
+int conv_cg(int KS, int Cin, int Cout) {
   if (KS != 3) return 4;
   const int g = (Cin + 7) / 8;
+  if (g == 2 && Cout > 16 && Cout % 16 == 0) return 4;
   return g <= 1 ? 1 : (g <= 2 ? 2 : 4);
 }
 
 size_t packed_elems(int Cout, int KS, int Cin) {
   const size_t nct = (size_t)((Cout + 16 * kMaxTM - 1) / (16 * kMaxTM)) * kMaxTM;
-  const int cg = conv_cg(KS, Cin);
+  const int cg = conv_cg(KS, Cin, Cout);
   if (cg < 4) return nct * ((KS * KS * cg + 3) / 4) * 512;
   const size_t nchunk = (size_t)(Cin + kChunk - 1) / kChunk;
   return nct * KS * KS * nchunk * 512;
@@ -1386,7 +1396,7 @@ void dispatch_tiles(const ConvArgs& a, hipStream_t st) {
 template <typename T, typename TO>
 void dispatch_ks(const ConvArgs& a, int KS, hipStream_t st) {
   if (KS == 3) {
-    const int cg = conv_cg(3, a.Cx + a.C2);
+    const int cg = conv_cg(3, a.Cx + a.C2, a.Cout);
     if (cg == 1) dispatch_tiles<T, TO, 3, 1>(a, st);
     else if (cg == 2) dispatch_tiles<T, TO, 3, 2>(a, st);
     else dispatch_tiles<T, TO, 3, 4>(a, st);
@@ -1683,7 +1693,7 @@ static int pack_impl(const float* w, int Cout, int ksize, int Cin, int dtype, vo
   const int nchunk = (ci + kChunk - 1) / kChunk;
   const int blocks = (int)((total + 255) / 256);
   hipStream_t st = as_stream(stream);
-  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, ci) == 4) {
+  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, ci, co) == 4) {
     // 16-channel chunks (fits in the packed_elems allocation, which counts 32-channel chunks)
     const int n16 = (ci + 15) / 16;
     const size_t t16 = (size_t)((co + 16 * kMaxTM - 1) / (16 * kMaxTM)) * kMaxTM * 9 * n16 * 256;
@@ -1691,11 +1701,11 @@ static int pack_impl(const float* w, int Cout, int ksize, int Cin, int dtype, vo
                                                             static_cast<float*>(packed), transpose);
   } else if (dtype == APS_F32)
     k_pack<float><<<blocks, 256, 0, st>>>(w, co, ksize, ci, nchunk, total,
-                                          static_cast<float*>(packed), transpose, conv_cg(ksize, ci));
+                                          static_cast<float*>(packed), transpose, conv_cg(ksize, ci, co));
   else if (dtype == APS_BF16)
     k_pack<uint16_t><<<blocks, 256, 0, st>>>(w, co, ksize, ci, nchunk, total,
                                              static_cast<uint16_t*>(packed), transpose,
-                                             conv_cg(ksize, ci));
+                                             conv_cg(ksize, ci, co));
   else
     return APS_ERR_UNSUPPORTED;
   APS_LAUNCH_CHECK();
@@ -1747,7 +1757,7 @@ int aps_conv2d_fwd(const void* x, const void* x2, int N, int H, int W, int Cx, i
   a.ldy = ldy;
   a.relu = relu;
   hipStream_t st = as_stream(stream);
-  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, Cx + C2) == 4 &&
+  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, Cx + C2, Cout) == 4 &&
       !fp32_offsets_fit(mode, N, H, W, Cx, C2))
     return APS_ERR_UNSUPPORTED;
   if (dtype == APS_F32 && y_dtype == APS_F32) dispatch_ks<float, float>(a, ksize, st);
@@ -1787,10 +1797,10 @@ int aps_conv2d_bwd_data(const void* dy, const void* ymask, int ldy, int N, int H
   a.Cout = Cin;
   a.nchunk = (ldy + kChunk - 1) / kChunk;
   // the operator was packed for Cout input channels: the padded stride must give the same layout
-  const int kc = dtype == APS_F32 && ksize == 3 && conv_cg(3, ldy) == 4 ? 16 : kChunk;
-  if ((ldy + kc - 1) / kc != (Cout + kc - 1) / kc || conv_cg(ksize, ldy) != conv_cg(ksize, Cout))
+  const int kc = dtype == APS_F32 && ksize == 3 && conv_cg(3, ldy, Cin) == 4 ? 16 : kChunk;
+  if ((ldy + kc - 1) / kc != (Cout + kc - 1) / kc || conv_cg(ksize, ldy, Cin) != conv_cg(ksize, Cout, Cin))
     return APS_ERR_SHAPE;
-  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, ldy) == 4 &&
+  if (dtype == APS_F32 && ksize == 3 && conv_cg(3, ldy, Cin) == 4 &&
       !fp32_offsets_fit(a.mode == kModeReluMask ? APS_CONV_DIRECT : a.mode, N, H, W, ldy, 0))
     return APS_ERR_UNSUPPORTED;
   a.y = dX;
@@ -1937,7 +1947,7 @@ int aps_conv2d_fwd_pool(const void* x, const void* x2, int N, int H, int W, int 
   } else {
     return APS_ERR_ARG;
   }
-  if (Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2) != 4 || Cout % 16 || Cout <= 16)
+  if (Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2, Cout) != 4 || Cout % 16 || Cout <= 16)
     return APS_ERR_UNSUPPORTED;
   if ((size_t)N * H * W == 0) return APS_OK;
   if (!x || !packed_w || !bias || !y || !pooled || (mode == APS_CONV_UP2_CAT && !x2))
@@ -1993,7 +2003,7 @@ int aps_conv2d_fwd_head_ex(const void* x, const void* x2, int N, int H, int W, i
       return APS_ERR_UNSUPPORTED;
   }
   if (Cout != 32 && Cout != 64) return APS_ERR_UNSUPPORTED;
-  if (K > 80 || Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2) != 4) return APS_ERR_UNSUPPORTED;
+  if (K > 80 || Cx % 8 || C2 % 8 || conv_cg(3, Cx + C2, Cout) != 4) return APS_ERR_UNSUPPORTED;
   if (y && ldy < Cout) return APS_ERR_SHAPE;
   if (mode == APS_CONV_UP2_CAT) {
     if (!x2 || C2 <= 0) return APS_ERR_NULL;
