@@ -1012,32 +1012,51 @@ struct SamplerArgs {
   float* z;
 };
 
-// One hidden layer (16 outputs, ReLU) on MFMA: output grid WOUT x WOUT at image (oy, ox),
-// input grid WIN x WIN in LDS (pixel stride psin), output to Y (pixel stride PSO).
-template <typename T, int CG, int WIN, int WOUT, int PSO>
-__device__ inline void sampler_hidden(const T* Xin, int psin, T* Y, const T* wp, const float* bias,
-                                      int H, int W, int oy, int ox, int lane, int wave) {
+// LDS layout of a pixel's 8-channel groups.  bf16 with 16 channels: 32-byte pixels whose two
+// 16-byte halves swap on every other run of 8 pixels (an XOR swizzle), so the 16 lanes that read
+// one group of 16 consecutive pixels hit distinct LDS banks with no padding (the padded 48-byte
+// pixels it replaces held three blocks per CU instead of five).  Otherwise (fp32, or bf16 with 8
+// channels) a padded pixel stride with the groups in order.
+template <typename T, int NG>
+struct SLay {
+  static constexpr bool kSw = sizeof(T) == 2 && NG == 2;
+  static constexpr int kPs = kSw ? 16 : (sizeof(T) == 2 ? 8 : 8 * NG + 4);  // elements per pixel
+  static __device__ inline int at(int p, int g) {
+    if constexpr (kSw) return p * 16 + ((g ^ ((p >> 3) & 1)) << 3);
+    else return p * kPs + g * 8;
+  }
+};
+
+// One hidden layer (16 outputs, ReLU) on MFMA: output grid WOUT x WOUT at image (oy, ox), input
+// grid WIN x WIN in LDS (layout SLay<T, CG>), output to Y (layout SLay<T, 2>).
+template <typename T, int CG, int WIN, int WOUT>
+__device__ inline void sampler_hidden(const T* Xin, T* Y, const T* wp, const float* bias, int H, int W,
+                                      int oy, int ox, int lane, int wave) {
+  using LI = SLay<T, CG>;
+  using LO = SLay<T, 2>;
   constexpr int NPAIR = 9 * CG, STEPS = (NPAIR + 3) / 4, NPX = WOUT * WOUT;
   Frag<T> wf[STEPS];
-  int off[STEPS];  // this lane's LDS offset of its (tap, group) pair at each K step
+  int toff[STEPS], grp[STEPS];  // this lane's (tap, group) pair at each K step: pixel offset, group
 #pragma unroll
   for (int s = 0; s < STEPS; ++s) {
     frag_load(wf[s], wp + ((size_t)s * 64 + lane) * 8);
     const int p = 4 * s + (lane >> 4);
     const int tap = p < NPAIR ? p / CG : 0, g = p < NPAIR ? p % CG : 0;  // padded pairs: zero weights
-    off[s] = ((tap / 3) * WIN + tap % 3) * psin + g * 8;
+    toff[s] = (tap / 3) * WIN + tap % 3;
+    grp[s] = g;
   }
   const f32x4 b = *reinterpret_cast<const f32x4*>(bias + 4 * (lane >> 4));  // added after the sum
+  const int co = 4 * (lane >> 4);  // this lane's four output channels
   for (int tile = wave; tile * 16 < NPX; tile += 4) {
     const int pix = tile * 16 + (lane & 15);
     const bool valid = pix < NPX;
     const int pp = valid ? pix : 0, r = pp / WOUT, c = pp - r * WOUT;
-    const T* base = Xin + (r * WIN + c) * psin;
+    const int p0 = r * WIN + c;
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) {
       Frag<T> bf;
-      frag_load(bf, base + off[s]);
+      frag_load(bf, Xin + LI::at(p0 + toff[s], grp[s]));
       acc = mma(wf[s], bf, acc);
     }
     if (valid) {
@@ -1046,35 +1065,38 @@ __device__ inline void sampler_hidden(const T* Xin, int psin, T* Y, const T* wp,
       float v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) v[q] = inside ? fmaxf(acc[q] + b[q], 0.f) : 0.f;
-      T* d = Y + pix * PSO + 4 * (lane >> 4);
+      T* d = Y + LO::at(pix, co >> 3) + (co & 7);
       if constexpr (sizeof(T) == 2) *reinterpret_cast<u16x4*>(d) = f2bf4(v[0], v[1], v[2], v[3]);
       else *reinterpret_cast<float4*>(d) = make_float4(v[0], v[1], v[2], v[3]);
     }
   }
 }
 
-// The 16 -> 1 output layer on MFMA over the 18x18 map: 16 output pixels per tile.
+// The 16 -> 1 output layer on MFMA over the 18x18 map (layout SLay<T, 2>): 16 output pixels per
+// tile.
 template <typename T>
-__device__ inline void sampler_out_mfma(const T* Xin, int psin, const T* wp, float bias, float* z, int H,
+__device__ inline void sampler_out_mfma(const T* Xin, const T* wp, float bias, float* z, int H,
                                         int W, int oy, int ox, int n, int lane, int wave) {
+  using LI = SLay<T, 2>;
   constexpr int STEPS = 5;
   Frag<T> wf[STEPS];
-  int off[STEPS];
+  int toff[STEPS], grp[STEPS];
 #pragma unroll
   for (int s = 0; s < STEPS; ++s) {
     frag_load(wf[s], wp + ((size_t)s * 64 + lane) * 8);
     const int p = 4 * s + (lane >> 4);
     const int tap = p < 18 ? p / 2 : 0, g = p < 18 ? p % 2 : 0;
-    off[s] = ((tap / 3) * 18 + tap % 3) * psin + g * 8;
+    toff[s] = (tap / 3) * 18 + tap % 3;
+    grp[s] = g;
   }
   for (int tile = wave; tile < 16; tile += 4) {
     const int r = tile, c = lane & 15;  // 16x16 outputs: one row per tile
-    const T* base = Xin + (r * 18 + c) * psin;
+    const int p0 = r * 18 + c;
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) {
       Frag<T> bf;
-      frag_load(bf, base + off[s]);
+      frag_load(bf, Xin + LI::at(p0 + toff[s], grp[s]));
       acc = mma(wf[s], bf, acc);
     }
     const int iy = oy + r, ix = ox + c;
@@ -1084,49 +1106,51 @@ __device__ inline void sampler_out_mfma(const T* Xin, int psin, const T* wp, flo
 
 template <typename T, int CG0>
 __global__ __launch_bounds__(256) void k_sampler_cnn(SamplerArgs a) {
-  constexpr int PS0 = CG0 * 8 + (sizeof(T) == 2 ? (CG0 == 2 ? 8 : 0) : 4);
-  constexpr int PS = sizeof(T) == 2 ? 24 : 20;  // 16 channels + pad
-  constexpr int X0N = 22 * 22 * PS0, H2N = 18 * 18 * PS;
+  using L0 = SLay<T, CG0>;
+  using L1 = SLay<T, 2>;
+  constexpr int X0N = 22 * 22 * L0::kPs, H2N = 18 * 18 * L1::kPs;
   __shared__ __attribute__((aligned(16))) T X0[X0N > H2N ? X0N : H2N];  // the 18x18 map reuses it
-  __shared__ __attribute__((aligned(16))) T H1[20 * 20 * PS];
+  __shared__ __attribute__((aligned(16))) T H1[20 * 20 * L1::kPs];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int tx0 = (blockIdx.x % a.ntx) * 16, ty0 = (blockIdx.x / a.ntx) * 16, n = blockIdx.z;
   const T* x = static_cast<const T*>(a.x);
   for (int it = tid; it < 22 * 22 * CG0; it += 256) {
     const int g = it % CG0, p = it / CG0, r = p / 22, c = p - r * 22;
     const int iy = ty0 - 3 + r, ix = tx0 - 3 + c;
-    T* d = X0 + p * PS0 + g * 8;
+    T* d = X0 + L0::at(p, g);
     if (iy >= 0 && iy < a.H && ix >= 0 && ix < a.W)
       copy8(d, x + (((size_t)n * a.H + iy) * a.W + ix) * a.C + g * 8);
     else
       zero8(d);
   }
   __syncthreads();
-  sampler_hidden<T, CG0, 22, 20, PS>(X0, PS0, H1, static_cast<const T*>(a.w[0]), a.b[0], a.H, a.W,
-                                     ty0 - 2, tx0 - 2, lane, wave);
+  sampler_hidden<T, CG0, 22, 20>(X0, H1, static_cast<const T*>(a.w[0]), a.b[0], a.H, a.W, ty0 - 2,
+                                 tx0 - 2, lane, wave);
   __syncthreads();
-  sampler_hidden<T, 2, 20, 18, PS>(H1, PS, X0, static_cast<const T*>(a.w[1]), a.b[1], a.H, a.W,
-                                   ty0 - 1, tx0 - 1, lane, wave);
+  sampler_hidden<T, 2, 20, 18>(H1, X0, static_cast<const T*>(a.w[1]), a.b[1], a.H, a.W, ty0 - 1,
+                               tx0 - 1, lane, wave);
   __syncthreads();
   if constexpr (sizeof(T) == 2) {
     // 16 -> 1 output layer on MFMA (row 0 of the 16-row tile is the output channel)
-    sampler_out_mfma<T>(X0, PS, static_cast<const T*>(a.w[2]), a.b[2][0], a.z, a.H, a.W, ty0, tx0, n, lane, wave);
+    sampler_out_mfma<T>(X0, static_cast<const T*>(a.w[2]), a.b[2][0], a.z, a.H, a.W, ty0, tx0, n, lane, wave);
   } else {
     // fp32: on the vector ALU, one output pixel per thread, since an fp32 MFMA tile would spend
     // 15 of its 16 rows on padding.  Weights are read from the packed buffer (output channel 0:
     // lane 16 (p % 4) of step p / 4 for pair p = 2 tap + ci / 8).
     const int r = tid >> 4, c = tid & 15;
     const float* wp2 = static_cast<const float*>(a.w[2]);
+    const float* X0f = reinterpret_cast<const float*>(X0);
     float acc = 0.f;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      const float* px = reinterpret_cast<const float*>(X0) + ((r + tap / 3) * 18 + c + tap % 3) * PS;
+      const int pp = (r + tap / 3) * 18 + c + tap % 3;
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
+        const float* px = X0f + L1::at(pp, g);
         const int pr = 2 * tap + g;
         const float* wv = wp2 + ((pr / 4) * 64 + 16 * (pr % 4)) * 8;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc = fmaf(wv[e], px[g * 8 + e], acc);
+        for (int e = 0; e < 8; ++e) acc = fmaf(wv[e], px[e], acc);
       }
     }
     const int iy = ty0 + r, ix = tx0 + c;
