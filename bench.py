@@ -316,7 +316,7 @@ def bench_train(dev, steps=3, warmup=1):
 
 WEIGHTS = os.path.join(ROOT, "paper_2602_08642_amd", "weights", "c4_trained.npz")
 CSRC = os.path.join(ROOT, "paper_2602_08642_amd", "csrc")
-TRAFFIC_SOURCES = ("aps_common.h", "conv.hip", "net.hip")
+TRAFFIC_SOURCES = ("aps_common.h", "mfma_frag.h", "conv.hip", "net.hip")
 
 
 def source_digest(names=TRAFFIC_SOURCES):

@@ -8,6 +8,7 @@
 // 2x upsampling of a coarser tensor concatenated with a skip tensor (U-Net decoder).
 // Epilogue: bias, optional ReLU, store (f32 or bf16).
 #include "aps_common.h"
+#include "mfma_frag.h"
 
 using namespace aps;
 
@@ -83,20 +84,6 @@ __device__ inline void store8(uint16_t* p, const V8f& r) {
   for (int e = 0; e < 8; ++e) h[e] = f2bf(r.v[e]);
   *reinterpret_cast<u16x8*>(p) = h;
 }
-// raw copy (no conversion) for the direct / concat paths
-__device__ inline void copy8(float* d, const float* s) {
-  *reinterpret_cast<float4*>(d) = *reinterpret_cast<const float4*>(s);
-  *reinterpret_cast<float4*>(d + 4) = *reinterpret_cast<const float4*>(s + 4);
-}
-__device__ inline void copy8(uint16_t* d, const uint16_t* s) {
-  *reinterpret_cast<u16x8*>(d) = *reinterpret_cast<const u16x8*>(s);
-}
-__device__ inline void zero8(float* d) {
-  *reinterpret_cast<float4*>(d) = make_float4(0.f, 0.f, 0.f, 0.f);
-  *reinterpret_cast<float4*>(d + 4) = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-__device__ inline void zero8(uint16_t* d) { *reinterpret_cast<u16x8*>(d) = u16x8{0, 0, 0, 0, 0, 0, 0, 0}; }
-
 // Stage channels [ci, ci+8) of input pixel (iy, ix) into LDS.
 template <typename T>
 __device__ inline void stage8(const ConvArgs& a, int n, int iy, int ix, int ci, T* dst) {
@@ -143,37 +130,6 @@ __device__ inline void stage8(const ConvArgs& a, int n, int iy, int ix, int ci, 
       copy8(dst, x2 + (((size_t)n * a.H + iy) * a.W + ix) * a.C2 + (ci - a.Cx));
     }
   }
-}
-
-template <typename T>
-struct Frag;
-template <>
-struct Frag<float> {
-  float v[8];
-};
-template <>
-struct Frag<uint16_t> {
-  u16x8 v;
-};
-
-__device__ inline void frag_load(Frag<float>& f, const float* p) {
-  const float4 a = *reinterpret_cast<const float4*>(p);
-  const float4 b = *reinterpret_cast<const float4*>(p + 4);
-  f.v[0] = a.x; f.v[1] = a.y; f.v[2] = a.z; f.v[3] = a.w;
-  f.v[4] = b.x; f.v[5] = b.y; f.v[6] = b.z; f.v[7] = b.w;
-}
-__device__ inline void frag_load(Frag<uint16_t>& f, const uint16_t* p) {
-  f.v = *reinterpret_cast<const u16x8*>(p);
-}
-
-__device__ inline f32x4 mma(const Frag<float>& a, const Frag<float>& b, f32x4 c) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[e], b.v[e], c, 0, 0, 0);
-  return c;
-}
-__device__ inline f32x4 mma(const Frag<uint16_t>& a, const Frag<uint16_t>& b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a.v),
-                                                 __builtin_bit_cast(bf16x8, b.v), c, 0, 0, 0);
 }
 
 template <typename TO>
@@ -994,167 +950,6 @@ bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
       case kModeReluMask: launch_conv_lds_m<kModeReluMask, 0>(a, st); return true;
       default: return false;
     }
-  }
-}
-
-// ---- fused sampler CNN ----------------------------------------------------------------------
-// The three 3x3 'same' convolutions of the sampler (Cin -> 16, ReLU; 16 -> 16, ReLU; 16 -> 1)
-// in one kernel.  A block stages its 22x22 input tile (16x16 outputs + 3-px halo) once; the two
-// intermediates (20x20 and 18x18 pixels x 16 channels) stay in LDS, zero outside the image and
-// rounded to T, as the layer-by-layer path stores them.  K enumerates (tap, 8-channel group)
-// pairs as in k_conv's CG < 4 layout (same packed weights); MFMA n-tiles are 16 consecutive
-// pixels of a layer's output grid, so B fragments are gathered per lane.
-struct SamplerArgs {
-  const void* x;
-  int N, H, W, C, ntx;
-  const void* w[3];  // packed weights of the three layers
-  const float* b[3];
-  float* z;
-};
-
-// LDS layout of a pixel's 8-channel groups.  bf16 with 16 channels: 32-byte pixels whose two
-// 16-byte halves swap on every other run of 8 pixels (an XOR swizzle), so the 16 lanes that read
-// one group of 16 consecutive pixels hit distinct LDS banks with no padding (the padded 48-byte
-// pixels it replaces held three blocks per CU instead of five).  Otherwise (fp32, or bf16 with 8
-// channels) a padded pixel stride with the groups in order.
-template <typename T, int NG>
-struct SLay {
-  static constexpr bool kSw = sizeof(T) == 2 && NG == 2;
-  static constexpr int kPs = kSw ? 16 : (sizeof(T) == 2 ? 8 : 8 * NG + 4);  // elements per pixel
-  static __device__ inline int at(int p, int g) {
-    if constexpr (kSw) return p * 16 + ((g ^ ((p >> 3) & 1)) << 3);
-    else return p * kPs + g * 8;
-  }
-};
-
-// One hidden layer (16 outputs, ReLU) on MFMA: output grid WOUT x WOUT at image (oy, ox), input
-// grid WIN x WIN in LDS (layout SLay<T, CG>), output to Y (layout SLay<T, 2>).
-template <typename T, int CG, int WIN, int WOUT>
-__device__ inline void sampler_hidden(const T* Xin, T* Y, const T* wp, const float* bias, int H, int W,
-                                      int oy, int ox, int lane, int wave) {
-  using LI = SLay<T, CG>;
-  using LO = SLay<T, 2>;
-  constexpr int NPAIR = 9 * CG, STEPS = (NPAIR + 3) / 4, NPX = WOUT * WOUT;
-  Frag<T> wf[STEPS];
-  int toff[STEPS], grp[STEPS];  // this lane's (tap, group) pair at each K step: pixel offset, group
-#pragma unroll
-  for (int s = 0; s < STEPS; ++s) {
-    frag_load(wf[s], wp + ((size_t)s * 64 + lane) * 8);
-    const int p = 4 * s + (lane >> 4);
-    const int tap = p < NPAIR ? p / CG : 0, g = p < NPAIR ? p % CG : 0;  // padded pairs: zero weights
-    toff[s] = (tap / 3) * WIN + tap % 3;
-    grp[s] = g;
-  }
-  const f32x4 b = *reinterpret_cast<const f32x4*>(bias + 4 * (lane >> 4));  // added after the sum
-  const int co = 4 * (lane >> 4);  // this lane's four output channels
-  for (int tile = wave; tile * 16 < NPX; tile += 4) {
-    const int pix = tile * 16 + (lane & 15);
-    const bool valid = pix < NPX;
-    const int pp = valid ? pix : 0, r = pp / WOUT, c = pp - r * WOUT;
-    const int p0 = r * WIN + c;
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < STEPS; ++s) {
-      Frag<T> bf;
-      frag_load(bf, Xin + LI::at(p0 + toff[s], grp[s]));
-      acc = mma(wf[s], bf, acc);
-    }
-    if (valid) {
-      const int iy = oy + r, ix = ox + c;
-      const bool inside = iy >= 0 && iy < H && ix >= 0 && ix < W;
-      float v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = inside ? fmaxf(acc[q] + b[q], 0.f) : 0.f;
-      T* d = Y + LO::at(pix, co >> 3) + (co & 7);
-      if constexpr (sizeof(T) == 2) *reinterpret_cast<u16x4*>(d) = f2bf4(v[0], v[1], v[2], v[3]);
-      else *reinterpret_cast<float4*>(d) = make_float4(v[0], v[1], v[2], v[3]);
-    }
-  }
-}
-
-// The 16 -> 1 output layer on MFMA over the 18x18 map (layout SLay<T, 2>): 16 output pixels per
-// tile.
-template <typename T>
-__device__ inline void sampler_out_mfma(const T* Xin, const T* wp, float bias, float* z, int H,
-                                        int W, int oy, int ox, int n, int lane, int wave) {
-  using LI = SLay<T, 2>;
-  constexpr int STEPS = 5;
-  Frag<T> wf[STEPS];
-  int toff[STEPS], grp[STEPS];
-#pragma unroll
-  for (int s = 0; s < STEPS; ++s) {
-    frag_load(wf[s], wp + ((size_t)s * 64 + lane) * 8);
-    const int p = 4 * s + (lane >> 4);
-    const int tap = p < 18 ? p / 2 : 0, g = p < 18 ? p % 2 : 0;
-    toff[s] = (tap / 3) * 18 + tap % 3;
-    grp[s] = g;
-  }
-  for (int tile = wave; tile < 16; tile += 4) {
-    const int r = tile, c = lane & 15;  // 16x16 outputs: one row per tile
-    const int p0 = r * 18 + c;
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < STEPS; ++s) {
-      Frag<T> bf;
-      frag_load(bf, Xin + LI::at(p0 + toff[s], grp[s]));
-      acc = mma(wf[s], bf, acc);
-    }
-    const int iy = oy + r, ix = ox + c;
-    if (lane < 16 && iy < H && ix < W) z[((size_t)n * H + iy) * W + ix] = acc[0] + bias;
-  }
-}
-
-template <typename T, int CG0>
-__global__ __launch_bounds__(256) void k_sampler_cnn(SamplerArgs a) {
-  using L0 = SLay<T, CG0>;
-  using L1 = SLay<T, 2>;
-  constexpr int X0N = 22 * 22 * L0::kPs, H2N = 18 * 18 * L1::kPs;
-  __shared__ __attribute__((aligned(16))) T X0[X0N > H2N ? X0N : H2N];  // the 18x18 map reuses it
-  __shared__ __attribute__((aligned(16))) T H1[20 * 20 * L1::kPs];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int tx0 = (blockIdx.x % a.ntx) * 16, ty0 = (blockIdx.x / a.ntx) * 16, n = blockIdx.z;
-  const T* x = static_cast<const T*>(a.x);
-  for (int it = tid; it < 22 * 22 * CG0; it += 256) {
-    const int g = it % CG0, p = it / CG0, r = p / 22, c = p - r * 22;
-    const int iy = ty0 - 3 + r, ix = tx0 - 3 + c;
-    T* d = X0 + L0::at(p, g);
-    if (iy >= 0 && iy < a.H && ix >= 0 && ix < a.W)
-      copy8(d, x + (((size_t)n * a.H + iy) * a.W + ix) * a.C + g * 8);
-    else
-      zero8(d);
-  }
-  __syncthreads();
-  sampler_hidden<T, CG0, 22, 20>(X0, H1, static_cast<const T*>(a.w[0]), a.b[0], a.H, a.W, ty0 - 2,
-                                 tx0 - 2, lane, wave);
-  __syncthreads();
-  sampler_hidden<T, 2, 20, 18>(H1, X0, static_cast<const T*>(a.w[1]), a.b[1], a.H, a.W, ty0 - 1,
-                               tx0 - 1, lane, wave);
-  __syncthreads();
-  if constexpr (sizeof(T) == 2) {
-    // 16 -> 1 output layer on MFMA (row 0 of the 16-row tile is the output channel)
-    sampler_out_mfma<T>(X0, static_cast<const T*>(a.w[2]), a.b[2][0], a.z, a.H, a.W, ty0, tx0, n, lane, wave);
-  } else {
-    // fp32: on the vector ALU, one output pixel per thread, since an fp32 MFMA tile would spend
-    // 15 of its 16 rows on padding.  Weights are read from the packed buffer (output channel 0:
-    // lane 16 (p % 4) of step p / 4 for pair p = 2 tap + ci / 8).
-    const int r = tid >> 4, c = tid & 15;
-    const float* wp2 = static_cast<const float*>(a.w[2]);
-    const float* X0f = reinterpret_cast<const float*>(X0);
-    float acc = 0.f;
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int pp = (r + tap / 3) * 18 + c + tap % 3;
-#pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        const float* px = X0f + L1::at(pp, g);
-        const int pr = 2 * tap + g;
-        const float* wv = wp2 + ((pr / 4) * 64 + 16 * (pr % 4)) * 8;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) acc = fmaf(wv[e], px[e], acc);
-      }
-    }
-    const int iy = ty0 + r, ix = tx0 + c;
-    if (iy < a.H && ix < a.W) a.z[((size_t)n * a.H + iy) * a.W + ix] = acc + a.b[2][0];
   }
 }
 
@@ -2077,38 +1872,3 @@ int aps_conv2d_fwd_head_ex(const void* x, const void* x2, int N, int H, int W, i
 }
 
 }  // extern "C"
-
-namespace aps {
-int sampler_cnn(const void* x, int N, int H, int W, int C, int Cin, const void* w0, const float* b0,
-                const void* w1, const float* b1, const void* w2, const float* b2, int dtype, float* z,
-                hipStream_t st) {
-  if (Cin > 16 || C % 8 || C < Cin) return APS_ERR_UNSUPPORTED;
-  SamplerArgs a{};
-  a.x = x;
-  a.N = N;
-  a.H = H;
-  a.W = W;
-  a.C = C;
-  a.ntx = (W + 15) / 16;
-  a.w[0] = w0;
-  a.w[1] = w1;
-  a.w[2] = w2;
-  a.b[0] = b0;
-  a.b[1] = b1;
-  a.b[2] = b2;
-  a.z = z;
-  dim3 grid(a.ntx * ((H + 15) / 16), 1, N);
-  const bool cg1 = Cin <= 8;
-  if (dtype == APS_BF16) {
-    if (cg1) k_sampler_cnn<uint16_t, 1><<<grid, 256, 0, st>>>(a);
-    else k_sampler_cnn<uint16_t, 2><<<grid, 256, 0, st>>>(a);
-  } else if (dtype == APS_F32) {
-    if (cg1) k_sampler_cnn<float, 1><<<grid, 256, 0, st>>>(a);
-    else k_sampler_cnn<float, 2><<<grid, 256, 0, st>>>(a);
-  } else {
-    return APS_ERR_UNSUPPORTED;
-  }
-  APS_LAUNCH_CHECK();
-  return APS_OK;
-}
-}  // namespace aps

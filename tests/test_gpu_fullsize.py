@@ -77,11 +77,11 @@ def test_sampler_1080p_matches_oracle(ops, cin, dtype):
     z, s = ops.density_predict(net, xd, 0.25)
     rec, zc = _nets.sampler_chain(ops, net, xd)
     what = f"sampler 1080p {str(dtype)[6:]}"
-    if dtype == torch.bfloat16:
-        assert torch.equal(z, zc)
-    else:   # the fused kernel's output layer sums on the vector ALU in another order
-        assert_mag_close(z.cpu(), zc.cpu(), zc.abs().cpu() + float(zc.abs().mean()), 1e-5,
-                         what=f"{what} fused vs chain")
+    # the fused kernel sums K in another order than the layer chain (bf16: an intermediate may
+    # round one ulp apart)
+    tol = 2.0 ** -6 if dtype == torch.bfloat16 else 1e-5
+    assert_mag_close(z.cpu(), zc.cpu(), zc.abs().cpu() + float(zc.abs().mean()), tol,
+                     what=f"{what} fused vs chain")
     wq = _wq(w, dtype)
     _nets.check_layers(rec, wq, {l["name"]: l["relu"] for l in spec}, LAYER_TOL[dtype], what)
     layers = [(wq[l["name"]][0], wq[l["name"]][1], l["relu"]) for l in spec]
