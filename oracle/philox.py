@@ -3,7 +3,8 @@
 
 The paper draws one uniform variate u_i per pixel for stochastic rounding (Sec. 4.2,
 eq. holdout) and does not fix the generator; this implementation keys Philox with the 64-bit
-scene seed and counts with (pixel, frame, stream, j).  u = (word0 >> 8) * 2^-24 lies in
+scene seed and counts with (pixel div 4, frame, stream, j): the four output words of one
+block serve four consecutive pixels (word pixel mod 4).  u = (word >> 8) * 2^-24 lies in
 [0, 1 - 2^-24] and is exact in binary32 and binary64.
 """
 import numpy as np
@@ -37,9 +38,11 @@ STREAM_U = 0
 
 
 def uniform24(seed: int, pixel, frame: int, stream: int = STREAM_U, j: int = 0):
-    """u in [0, 1): 24 high bits of output word 0, counter (pixel, frame, stream, j)."""
+    """u in [0, 1): 24 high bits of output word (pixel mod 4) of the block with counter
+    (pixel div 4, frame, stream, j)."""
     seed = int(seed)
     pixel = np.asarray(pixel, dtype=np.uint64)
-    w = philox4x32_10(pixel, np.uint64(frame), np.uint64(stream), np.uint64(j),
-                      seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)[0]
+    words = philox4x32_10(pixel >> np.uint64(2), np.uint64(frame), np.uint64(stream), np.uint64(j),
+                          seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    w = np.choose((pixel & np.uint64(3)).astype(np.int64), words)
     return (w >> np.uint64(8)).astype(np.float64) * 2.0 ** -24

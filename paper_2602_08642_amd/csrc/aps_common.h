@@ -57,20 +57,26 @@ __device__ inline uint16_t f2t<uint16_t>(float v) { return f2bf(v); }
 __device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    // one 32 x 32 -> 64-bit multiply (v_mad_u64_u32) gives both halves of a product
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                   (uint32_t)p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
   return c;
 }
 
-// u in [0, 1 - 2^-24]: top 24 bits of word 0 for counter (pixel, frame, stream 0, 0).
+// u in [0, 1 - 2^-24]: top 24 bits of word (pixel mod 4) of the block with counter
+// (pixel div 4, frame, stream 0, 0); one block serves four consecutive pixels.
+__device__ inline float u24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+__device__ inline uint4 uniform_block(uint64_t seed, uint32_t quad, uint32_t frame) {
+  return philox4x32_10(make_uint4(quad, frame, 0u, 0u), (uint32_t)seed, (uint32_t)(seed >> 32));
+}
 __device__ inline float uniform24(uint64_t seed, uint32_t pixel, uint32_t frame) {
-  const uint4 r = philox4x32_10(make_uint4(pixel, frame, 0u, 0u), (uint32_t)seed,
-                                (uint32_t)(seed >> 32));
-  return (float)(r.x >> 8) * 0x1p-24f;
+  const uint4 r = uniform_block(seed, pixel >> 2, frame);
+  const uint32_t k = pixel & 3u;
+  return u24(k == 0 ? r.x : k == 1 ? r.y : k == 2 ? r.z : r.w);
 }
 
 // u of the sampling step: Philox per pixel (tex == nullptr), or a T x T threshold texture

@@ -14,8 +14,8 @@ using namespace aps;
 
 namespace {
 
-constexpr int kNormElems = 2048;  // pixels per block of the softmax partial reductions
-constexpr int kMaskBlock = 256;   // pixels per block of the sample-list offsets
+constexpr int kNormElems = 4096;  // pixels per block of the softmax partial reductions
+constexpr int kMaskBlock = 1024;  // pixels per block of the sample mask (4 per thread)
 constexpr int kMaxTexSize = 4096;  // largest blue-noise texture side accepted
 
 // ------------------------------------------------------------------ normalisation
@@ -50,14 +50,11 @@ __global__ __launch_bounds__(256) void k_norm_partial(const float* __restrict__ 
   if (threadIdx.x == 0) part[(size_t)n * nb + b] = make_float2(m, (ss[0] + ss[1]) + (ss[2] + ss[3]));
 }
 
-// One block per image: combine partials into (max, sum) with a fixed order.
-__global__ __launch_bounds__(256) void k_norm_combine(const float2* __restrict__ part, int nb,
-                                                      float2* __restrict__ stats) {
-  const int n = blockIdx.x;
-  const float2* p = part + (size_t)n * nb;
+// Combine one image's partials into (max, sum) with a fixed order (a block of 256 threads;
+// every caller gets the same result from the same partials).
+__device__ inline float2 norm_combine_block(const float2* __restrict__ p, int nb, float* red) {
   float m = -INFINITY;
   for (int b = threadIdx.x; b < nb; b += 256) m = fmaxf(m, p[b].x);
-  __shared__ float red[4];
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -68,135 +65,228 @@ __global__ __launch_bounds__(256) void k_norm_combine(const float2* __restrict__
   e = wave_sum(e);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
   __syncthreads();
-  if (threadIdx.x == 0) stats[n] = make_float2(m, (red[0] + red[1]) + (red[2] + red[3]));
+  const float sum = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return make_float2(m, sum);
 }
 
-// s = f*B + (1-f)*B*Npx * exp(z - max) / sum
+// One block per image: the combined (max, sum) for the backward pass.
+__global__ __launch_bounds__(256) void k_norm_combine(const float2* __restrict__ part, int nb,
+                                                      float2* __restrict__ stats) {
+  __shared__ float red[4];
+  const float2 ms = norm_combine_block(part + (size_t)blockIdx.x * nb, nb, red);
+  if (threadIdx.x == 0) stats[blockIdx.x] = ms;
+}
+
+// s = f*B + (1-f)*B*Npx * exp(z - max) / sum over kNormApply pixels per block (4 per thread);
+// each block combines the image's partials itself (a few thousand L2-resident values) instead
+// of waiting for a combine launch.
+constexpr int kNormPer = 4, kNormApply = 256 * kNormPer;
 __global__ __launch_bounds__(256) void k_norm_apply(const float* __restrict__ z, int npx,
-                                                    const float2* __restrict__ stats, float c0,
-                                                    float c1, float* __restrict__ s,
-                                                    uint32_t* st) {
+                                                    const float2* __restrict__ part, int nbp,
+                                                    float c0, float c1, int vec,
+                                                    float* __restrict__ s, uint32_t* st) {
   const int n = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= npx) return;
-  const float2 ms = stats[n];
-  const float zi = z[(size_t)n * npx + i];
-  const float v = c0 + c1 * (expf(zi - ms.x) / ms.y);
-  if (!isfinite(v)) status_or(st, APS_STATUS_NONFINITE);
-  s[(size_t)n * npx + i] = v;
+  __shared__ float red[4];
+  const float2 ms = norm_combine_block(part + (size_t)n * nbp, nbp, red);
+  const int i0 = blockIdx.x * kNormApply + threadIdx.x * kNormPer;
+  const float* zi = z + (size_t)n * npx;
+  float* si = s + (size_t)n * npx;
+  bool bad = false;
+  if (vec && i0 + kNormPer <= npx) {
+#pragma unroll
+    for (int k = 0; k < kNormPer; k += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(zi + i0 + k);
+      const float4 o = make_float4(c0 + c1 * (expf(v.x - ms.x) / ms.y), c0 + c1 * (expf(v.y - ms.x) / ms.y),
+                                   c0 + c1 * (expf(v.z - ms.x) / ms.y), c0 + c1 * (expf(v.w - ms.x) / ms.y));
+      bad |= !isfinite(o.x) || !isfinite(o.y) || !isfinite(o.z) || !isfinite(o.w);
+      *reinterpret_cast<float4*>(si + i0 + k) = o;
+    }
+  } else {
+    for (int k = 0; k < kNormPer; ++k) {
+      if (i0 + k >= npx) break;
+      const float v = c0 + c1 * (expf(zi[i0 + k] - ms.x) / ms.y);
+      bad |= !isfinite(v);
+      si[i0 + k] = v;
+    }
+  }
+  if (bad) status_or(st, APS_STATUS_NONFINITE);
 }
 
 // ------------------------------------------------------------------ sample mask
-__global__ __launch_bounds__(kMaskBlock) void k_mask_count(const float* __restrict__ s,
-                                                           int npix, uint64_t seed, uint32_t frame,
-                                                           USource us, int rounding,
-                                                           uint8_t* __restrict__ count,
-                                                           float* __restrict__ p_out,
-                                                           int32_t* __restrict__ block_sum,
-                                                           uint32_t* st) {
-  const int i = blockIdx.x * kMaskBlock + threadIdx.x;
-  int c = 0;
-  if (i < npix) {
-    const float si = s[i];
-    float p = 0.f;
-    if (!(si >= 0.f) || !isfinite(si)) {
-      status_or(st, APS_STATUS_NONFINITE);
-    } else {
-      const float fl = floorf(si);
-      p = si - fl;  // exact in binary32
-      // stochastic: floor(s) + [u < p] (eq. holdout); holdout always requested: floor(s) + [p > 0]
-      // (straight-through, Gumbel-Softmax); deterministic: round(s) (Sec. 4.1 eq. kuz_fw)
-      int extra;
-      if (rounding == APS_ROUND_STOCHASTIC) extra = draw_u(us, seed, (uint32_t)i, frame) < p ? 1 : 0;
-      else if (rounding == APS_ROUND_HOLDOUT) extra = p > 0.f ? 1 : 0;
-      else extra = p >= 0.5f ? 1 : 0;
-      if (fl > 254.f) {
-        status_or(st, APS_STATUS_COUNT_OVERFLOW);
-        c = 255;
-      } else {
-        c = (int)fl + extra;
-        if (c > 255) {
-          status_or(st, APS_STATUS_COUNT_OVERFLOW);
-          c = 255;
-        }
-      }
-    }
-    count[i] = (uint8_t)c;
-    if (p_out) p_out[i] = p;
+// Two launches: counts with per-block sums, then offsets and the compact list, where each block
+// adds up the sums of the blocks before it (at most a few thousand L2-resident integers) rather
+// than waiting for a separate scan launch.  A thread owns kMaskPer consecutive pixels, so a
+// block's exclusive scan is one scan over its 256 thread totals.
+constexpr int kMaskPer = 4;
+
+// Count of pixel i from s_i (eq. holdout): stochastic floor(s) + [u < p]; holdout always
+// requested floor(s) + [p > 0] (straight-through, Gumbel-Softmax); deterministic round(s)
+// (Sec. 4.1 eq. kuz_fw).  p = s - floor(s) is exact in binary32.
+__device__ inline int mask_count_one(float si, float u, int rounding, float& p, uint32_t* st) {
+  p = 0.f;
+  if (!(si >= 0.f) || !isfinite(si)) {
+    status_or(st, APS_STATUS_NONFINITE);
+    return 0;
   }
-  __shared__ int red[kMaskBlock / 64];
-  const int ws = wave_isum(c);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
-  __syncthreads();
-  if (threadIdx.x == 0) block_sum[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  const float fl = floorf(si);
+  p = si - fl;
+  int extra;
+  if (rounding == APS_ROUND_STOCHASTIC) extra = u < p ? 1 : 0;
+  else if (rounding == APS_ROUND_HOLDOUT) extra = p > 0.f ? 1 : 0;
+  else extra = p >= 0.5f ? 1 : 0;
+  int c = fl > 254.f ? 256 : (int)fl + extra;
+  if (c > 255) {
+    status_or(st, APS_STATUS_COUNT_OVERFLOW);
+    c = 255;
+  }
+  return c;
 }
 
-// Single block: exclusive scan of the block sums, and the total.
-__global__ __launch_bounds__(1024) void k_mask_scan(const int32_t* __restrict__ block_sum, int nb,
-                                                    int32_t* __restrict__ block_off,
-                                                    int32_t* __restrict__ total) {
-  const int t = threadIdx.x;
-  const int per = (nb + 1023) / 1024;
-  const int b0 = t * per, b1 = min(b0 + per, nb);
-  // up to kPer sums per thread are loaded into registers together (one memory round trip
-  // instead of one per loop iteration); longer segments take the loop
-  constexpr int kPer = 32;
-  int v[kPer];
-  int local = 0;
-  if (per <= kPer) {
+// block sum over a block of 256 threads (fixed tree)
+__device__ inline int block_isum(int v, int* red) {
+  v = wave_isum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const int r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_mask_count(const float* __restrict__ s, int npix,
+                                                    uint64_t seed, uint32_t frame, USource us,
+                                                    int rounding, int vec,
+                                                    uint8_t* __restrict__ count,
+                                                    float* __restrict__ p_out,
+                                                    int32_t* __restrict__ block_sum, uint32_t* st) {
+  const int i0 = blockIdx.x * kMaskBlock + threadIdx.x * kMaskPer;
+  float sv[kMaskPer];
+  const bool full = vec && i0 + kMaskPer <= npix;
+  if (full) {
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) v[k] = b0 + k < b1 ? block_sum[b0 + k] : 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) local += v[k];
+    for (int k = 0; k < kMaskPer; k += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(s + i0 + k);
+      sv[k] = v.x;
+      sv[k + 1] = v.y;
+      sv[k + 2] = v.z;
+      sv[k + 3] = v.w;
+    }
   } else {
-    for (int b = b0; b < b1; ++b) local += block_sum[b];
+#pragma unroll
+    for (int k = 0; k < kMaskPer; ++k) sv[k] = i0 + k < npix ? s[i0 + k] : 0.f;
   }
-  __shared__ int wsum[16];
-  const int incl = wave_iscan(local);
+  // u of the thread's pixels: one Philox block per four (i0 is a multiple of 4)
+  float u[kMaskPer];
+  if (rounding == APS_ROUND_STOCHASTIC) {
+    if (full && !us.tex) {
+#pragma unroll
+      for (int q = 0; q < kMaskPer / 4; ++q) {
+        const uint4 r = uniform_block(seed, (uint32_t)(i0 / 4 + q), frame);
+        u[4 * q] = u24(r.x);
+        u[4 * q + 1] = u24(r.y);
+        u[4 * q + 2] = u24(r.z);
+        u[4 * q + 3] = u24(r.w);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kMaskPer; ++k) u[k] = i0 + k < npix ? draw_u(us, seed, (uint32_t)(i0 + k), frame) : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMaskPer; ++k) u[k] = 0.f;
+  }
+  int c[kMaskPer];
+  float p[kMaskPer];
+  int tsum = 0;
+#pragma unroll
+  for (int k = 0; k < kMaskPer; ++k) {
+    c[k] = i0 + k < npix ? mask_count_one(sv[k], u[k], rounding, p[k], st) : 0;
+    tsum += c[k];
+  }
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < kMaskPer / 4; ++q)
+      reinterpret_cast<uint32_t*>(count + i0)[q] =
+          (uint32_t)c[4 * q] | ((uint32_t)c[4 * q + 1] << 8) | ((uint32_t)c[4 * q + 2] << 16) |
+          ((uint32_t)c[4 * q + 3] << 24);
+    if (p_out) {
+#pragma unroll
+      for (int k = 0; k < kMaskPer; k += 4)
+        *reinterpret_cast<float4*>(p_out + i0 + k) = make_float4(p[k], p[k + 1], p[k + 2], p[k + 3]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMaskPer; ++k)
+      if (i0 + k < npix) {
+        count[i0 + k] = (uint8_t)c[k];
+        if (p_out) p_out[i0 + k] = p[k];
+      }
+  }
+  __shared__ int red[4];
+  const int bs = block_isum(tsum, red);
+  if (threadIdx.x == 0) block_sum[blockIdx.x] = bs;
+}
+
+__global__ __launch_bounds__(256) void k_mask_compact(const uint8_t* __restrict__ count, int npix,
+                                                      int vec, const int32_t* __restrict__ block_sum,
+                                                      int nb, int32_t* __restrict__ pixel_offset,
+                                                      int32_t* __restrict__ sample_pixel,
+                                                      int64_t capacity, int32_t* __restrict__ total,
+                                                      uint32_t* st) {
+  const int b = blockIdx.x, t = threadIdx.x;
+  __shared__ int red[4];
+  __shared__ int wsum[4];
+  // samples of the blocks before this one
+  int before = 0;
+  int j = t;
+  for (; j + 768 < b; j += 1024)  // four independent loads in flight per thread
+    before += (block_sum[j] + block_sum[j + 256]) + (block_sum[j + 512] + block_sum[j + 768]);
+  for (; j < b; j += 256) before += block_sum[j];
+  const int base = block_isum(before, red);
+  const int i0 = b * kMaskBlock + t * kMaskPer;
+  const bool full = vec && i0 + kMaskPer <= npix;
+  int c[kMaskPer];
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < kMaskPer / 4; ++q) {
+      const uint32_t w = reinterpret_cast<const uint32_t*>(count + i0)[q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[4 * q + k] = (int)((w >> (8 * k)) & 255u);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMaskPer; ++k) c[k] = i0 + k < npix ? (int)count[i0 + k] : 0;
+  }
+  int tsum = 0;
+#pragma unroll
+  for (int k = 0; k < kMaskPer; ++k) tsum += c[k];
+  const int incl = wave_iscan(tsum);
   if ((t & 63) == 63) wsum[t >> 6] = incl;
   __syncthreads();
-  if (t < 64) {
-    const int v = t < 16 ? wsum[t] : 0;
-    const int sc = wave_iscan(v);
-    if (t < 16) wsum[t] = sc - v;  // exclusive wave offsets
-  }
-  __syncthreads();
-  int run = wsum[t >> 6] + incl - local;
-  if (per <= kPer) {
+  int wbefore = 0;
+  for (int w = 0; w < (t >> 6); ++w) wbefore += wsum[w];
+  int off = base + wbefore + incl - tsum;
+  if (b == nb - 1 && t == 255) *total = off + tsum;
+  int o[kMaskPer];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      if (b0 + k < b1) block_off[b0 + k] = run;
-      run += v[k];
+  for (int k = 0; k < kMaskPer; ++k) {
+    o[k] = off;
+    if (i0 + k < npix) {
+      for (int j = 0; j < c[k]; ++j) {
+        if ((int64_t)off + j < capacity) sample_pixel[off + j] = i0 + k;
+        else status_or(st, APS_STATUS_CAPACITY);
+      }
     }
-  } else {
-    for (int b = b0; b < b1; ++b) {
-      block_off[b] = run;
-      run += block_sum[b];
-    }
+    off += c[k];
   }
-  if (t == 1023) *total = run;
-}
-
-__global__ __launch_bounds__(kMaskBlock) void k_mask_compact(const uint8_t* __restrict__ count,
-                                                             int npix,
-                                                             const int32_t* __restrict__ block_off,
-                                                             int32_t* __restrict__ pixel_offset,
-                                                             int32_t* __restrict__ sample_pixel,
-                                                             int64_t capacity, uint32_t* st) {
-  const int i = blockIdx.x * kMaskBlock + threadIdx.x;
-  const int c = i < npix ? (int)count[i] : 0;
-  __shared__ int wsum[kMaskBlock / 64];
-  const int incl = wave_iscan(c);
-  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
-  __syncthreads();
-  int before = 0;
-  for (int w = 0; w < (threadIdx.x >> 6); ++w) before += wsum[w];
-  if (i >= npix) return;
-  const int off = block_off[blockIdx.x] + before + incl - c;
-  pixel_offset[i] = off;
-  for (int j = 0; j < c; ++j) {
-    if ((int64_t)off + j < capacity) sample_pixel[off + j] = i;
-    else status_or(st, APS_STATUS_CAPACITY);
+  if (full) {
+#pragma unroll
+    for (int k = 0; k < kMaskPer; k += 4)
+      *reinterpret_cast<int4*>(pixel_offset + i0 + k) = make_int4(o[k], o[k + 1], o[k + 2], o[k + 3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMaskPer; ++k)
+      if (i0 + k < npix) pixel_offset[i0 + k] = o[k];
   }
 }
 
@@ -694,13 +784,13 @@ __global__ __launch_bounds__(256) void k_features_bwd(int kind, const float4* __
 }
 
 // ------------------------------------------------------------------ static mask scratch
-// The no-allocation variant of the mask keeps its block sums and block offsets in this
+// The no-allocation variant of the mask keeps its block sums in this
 // file-scope array instead of a caller workspace.  Each device holds its own copy; host code
 // reaches it only through the address hipGetSymbolAddress returns for that device (the
 // array's name is a host-side stand-in, not a device address).
 constexpr size_t kMaskStaticPixels = size_t(1) << 25;  // 33.5M px: four 3840x2160 frames
 constexpr size_t kMaskStaticBlocks = kMaskStaticPixels / kMaskBlock;
-static __device__ __align__(256) int32_t scratch[2 * kMaskStaticBlocks];  // 1 MiB
+static __device__ __align__(256) int32_t scratch[kMaskStaticBlocks];  // 128 KiB
 
 constexpr int kMaxDevices = 64;
 std::atomic<int32_t*> g_scratch_ptr[kMaxDevices];
@@ -733,8 +823,8 @@ int32_t* mask_scratch(hipStream_t st) {
   return p;
 }
 
-// Counts, block sums, their scan and the compaction (eq. holdout); the two int32 arrays of
-// nb entries come from ws or, with use_static, from the device's static scratch.
+// Counts, block sums and the compaction (eq. holdout); the int32 array of nb block sums comes
+// from ws or, with use_static, from the device's static scratch.
 int sample_mask_impl(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,
                      const float* u_tex, int tex_size, int rounding, uint8_t* count,
                      int32_t* pixel_offset, int32_t* sample_pixel, int64_t capacity,
@@ -746,7 +836,7 @@ int sample_mask_impl(const float* s, int N, int H, int W, uint64_t seed, uint32_
       rounding != APS_ROUND_DETERMINISTIC)
     return APS_ERR_ARG;
   const size_t npix = (size_t)N * H * W;
-  if (npix > 0x7fffffffull) return APS_ERR_SHAPE;
+  if (npix > 0x7fffffffull - kMaskBlock) return APS_ERR_SHAPE;  // pixel indices stay in int
   if (use_static && npix > kMaskStaticPixels) return APS_ERR_TOO_LARGE;
   if (!total) return APS_ERR_NULL;
   hipStream_t st = as_stream(stream);
@@ -765,15 +855,16 @@ int sample_mask_impl(const float* s, int N, int H, int W, uint64_t seed, uint32_
     if (!ws || ws_bytes < aps_sample_mask_workspace_size(N, H, W)) return APS_ERR_WORKSPACE;
     bsum = static_cast<int32_t*>(ws);
   }
-  // every entry of both arrays is written before it is read (k_mask_count writes all nb block
-  // sums, k_mask_scan all nb offsets): nothing has to start at zero
-  int32_t* boff = bsum + nb;
+  // every block sum is written (k_mask_count) before it is read (k_mask_compact): nothing has
+  // to start at zero
   const USource us{u_tex, (uint32_t)tex_size, (uint32_t)H, (uint32_t)W};
-  k_mask_count<<<nb, kMaskBlock, 0, st>>>(s, (int)npix, seed, frame, us, rounding, count, p_out,
-                                          bsum, dev_status);
-  k_mask_scan<<<1, 1024, 0, st>>>(bsum, nb, boff, total);
-  k_mask_compact<<<nb, kMaskBlock, 0, st>>>(count, (int)npix, boff, pixel_offset, sample_pixel,
-                                            capacity, dev_status);
+  const int vec = ((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(count) |
+                    reinterpret_cast<uintptr_t>(pixel_offset) | reinterpret_cast<uintptr_t>(p_out)) &
+                   15) == 0;
+  k_mask_count<<<nb, 256, 0, st>>>(s, (int)npix, seed, frame, us, rounding, vec, count, p_out,
+                                   bsum, dev_status);
+  k_mask_compact<<<nb, 256, 0, st>>>(count, (int)npix, vec, bsum, nb, pixel_offset, sample_pixel,
+                                     capacity, total, dev_status);
   APS_LAUNCH_CHECK();
   return APS_OK;
 }
@@ -796,19 +887,19 @@ int aps_normalize_density(const float* z, int N, int H, int W, float budget_spp,
   if ((size_t)N * H * W == 0) return APS_OK;
   if (!z || !s_out) return APS_ERR_NULL;
   if (!(budget_spp > 0.f) || !(uniform_frac >= 0.f && uniform_frac <= 1.f)) return APS_ERR_ARG;
-  if ((size_t)H * W > 0x7fffffffull) return APS_ERR_SHAPE;
+  if ((size_t)H * W > 0x7fffffffull - kNormApply) return APS_ERR_SHAPE;
   if (ws_bytes < aps_normalize_workspace_size(N, H, W) || !ws) return APS_ERR_WORKSPACE;
   const int npx = H * W;
   const int nb = (npx + kNormElems - 1) / kNormElems;
   float2* part = static_cast<float2*>(ws);
-  float2* stats = part + (size_t)N * nb;
   hipStream_t st = as_stream(stream);
   k_norm_partial<<<dim3(nb, N), 256, 0, st>>>(z, npx, nb, part);
-  k_norm_combine<<<N, 256, 0, st>>>(part, nb, stats);
   const float c0 = uniform_frac * budget_spp;
   const float c1 = (1.f - uniform_frac) * budget_spp * (float)npx;
-  k_norm_apply<<<dim3((npx + 255) / 256, N), 256, 0, st>>>(z, npx, stats, c0, c1, s_out,
-                                                           dev_status);
+  const int vec = ((reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(s_out)) & 15) == 0 &&
+                  npx % 4 == 0;
+  k_norm_apply<<<dim3((npx + kNormApply - 1) / kNormApply, N), 256, 0, st>>>(
+      z, npx, part, nb, c0, c1, vec, s_out, dev_status);
   APS_LAUNCH_CHECK();
   return APS_OK;
 }
@@ -816,7 +907,7 @@ int aps_normalize_density(const float* z, int N, int H, int W, float budget_spp,
 size_t aps_sample_mask_workspace_size(int N, int H, int W) {
   const size_t npix = (size_t)N * H * W;
   const size_t nb = (npix + kMaskBlock - 1) / kMaskBlock;
-  return 2 * nb * sizeof(int32_t) + 256;
+  return nb * sizeof(int32_t) + 256;
 }
 
 int aps_sample_mask(const float* s, int N, int H, int W, uint64_t seed, uint32_t frame,

@@ -36,6 +36,17 @@ def test_uniform24_exact_and_uniform():
     assert not np.array_equal(u[:10], u3)
 
 
+def test_uniform24_uses_the_four_words_of_a_block():
+    """Pixels 4q .. 4q+3 take words 0..3 of the Philox block with counter (q, frame, 0, 0),
+    the same block the KAT-pinned generator gives for that counter."""
+    seed, frame = 0x0123456789ABCDEF, 7
+    for q in (0, 1, 12345, 2 ** 29 + 3):
+        words = philox.philox4x32_10(q, frame, 0, 0, seed & 0xFFFFFFFF, seed >> 32)
+        for k in range(4):
+            u = philox.uniform24(seed, np.array([4 * q + k], np.uint64), frame)[0]
+            assert u == (int(words[k]) >> 8) * 2.0 ** -24
+
+
 def test_conv_matches_library():
     g = torch.Generator().manual_seed(0)
     x = torch.randn(2, 9, 7, 5, generator=g, dtype=torch.float64)
