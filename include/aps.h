@@ -141,7 +141,9 @@ int aps_normalize_density(const float* z, int N, int H, int W, float budget_spp,
                           uint32_t* dev_status, void* stream);
 
 /* Sampler CNN on features feat [N,H,W,C] (dtype of the net) -> z (optional, float32 [N,H,W])
- * -> s float32 [N,H,W]. */
+ * -> s float32 [N,H,W].  The configured shape (3x3 layers Cin -> 16 -> 16 -> 1, ReLU on the
+ * hidden layers) runs as one kernel; in bf16 it addresses one image's features with 32-bit
+ * byte offsets, so H*W*C*2 < 2^31 (APS_ERR_SHAPE otherwise). */
 size_t aps_density_predict_workspace_size(int N, int H, int W, int width, int dtype);
 int aps_density_predict(const aps_net* net, const void* feat, int N, int H, int W, int C,
                         float budget_spp, float uniform_frac, float* z_out, float* s_out,
@@ -160,11 +162,12 @@ int aps_upsample_nearest2(const float* s_q, int N, int Hq, int Wq, float* s, voi
 
 /* ---------------------------------------------------------------- a3: sample mask
  * Sec. 4.2, eq. holdout: count = floor(s) + [u < p], p = s - floor(s) (exact in binary32),
- * u = (Philox4x32-10(key = seed, counter = (pixel, frame, 0, 0)).x >> 8) * 2^-24.
+ * u = (w >> 8) * 2^-24 with w the word (pixel mod 4) of Philox4x32-10(key = seed,
+ * counter = (pixel div 4, frame, 0, 0)): one block serves four consecutive pixels.
  * Outputs: count uint8 [N,H,W]; pixel_offset int32 [N,H,W] = exclusive prefix sum of count
  * in pixel order; sample_pixel int32 [capacity] = the pixel id of every requested sample,
  * ascending (the renderer's request list); total int32 (device) = sum of counts; p_out
- * (optional) float32 [N,H,W].  Bit-exact and deterministic.  N*H*W < 2^31.
+ * (optional) float32 [N,H,W].  Bit-exact and deterministic.  N*H*W <= 2^31 - 1 - 1024.
  * Capacity N*H*W*(B + 1) always suffices for budget-normalised s; entries past capacity are
  * dropped and flagged APS_STATUS_CAPACITY. */
 size_t aps_sample_mask_workspace_size(int N, int H, int W);
@@ -193,7 +196,7 @@ int aps_sample_mask_ex(const float* s, int N, int H, int W, uint64_t seed, uint3
 /* No-allocation variant of aps_sample_mask_ex, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
  * Same arguments, results and errors as aps_sample_mask_ex without ws / ws_bytes: the block
- * sums and block offsets live in a static device array of the library (1 MiB per device,
+ * sums live in a static device array of the library (128 KiB per device,
  * kept until the process ends; its address is looked up on the stream's device at the first
  * call there).  Limit: N*H*W <= 2^25 pixels (four 3840x2160 frames), else APS_ERR_TOO_LARGE
  * before anything is launched.  Nothing in the array has to start at zero (every entry is
