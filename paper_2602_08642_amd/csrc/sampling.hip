@@ -409,22 +409,33 @@ __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ s,
 }
 
 // ------------------------------------------------------------------ feature assembly
+// The forward feature transforms use the hardware base-2 logarithm and exponential
+// (v_log_f32, v_exp_f32, about one ulp): network inputs need about 1e-5 relative, and the
+// library-accurate log1p / log / exp / pow made the assembly bound by its arithmetic rather
+// than by its memory traffic.  The backward keeps the accurate functions.
+constexpr float kLn2 = 0.69314718055994531f, kLog2e = 1.4426950408889634f;
+__device__ inline float fast_log(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ inline float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+// log(1 + a) for a >= 0: 1 + a rounds by at most 2^-24, an absolute error of 6e-8 in the log
+__device__ inline float slog1p_fwd(float v) { return copysignf(fast_log(1.f + fabsf(v)), v); }
 __device__ inline float slog1p(float v) { return copysignf(log1pf(fabsf(v)), v); }
 
 // Evaluation tonemapper of the feedback loop (Sec. 5): log, curve tau(x; 0.5, 0.5) with
 // contrast 0.4, exposure 0, saturation 1, then the sRGB transfer function.
 __device__ inline float tau_eval(float x) {
   const float s = 0.5f, h = 0.5f;
-  if (x < s - 1.f) return 0.5f * s * expf((x + 1.f - s) / s);
+  if (x < s - 1.f) return 0.5f * s * fast_exp((x + 1.f - s) / s);
   if (x < 1.f - h) return 0.5f * (1.f + x);
-  return 1.f - 0.5f * h * expf(-(x + h - 1.f) / h);
+  return 1.f - 0.5f * h * fast_exp(-(x + h - 1.f) / h);
 }
 __device__ inline float srgb(float v) {
   v = fminf(fmaxf(v, 0.f), 1.f);
-  return v <= 0.0031308f ? 12.92f * v : 1.055f * powf(v, 1.f / 2.4f) - 0.055f;
+  // v^(1/2.4) = 2^(log2(v) / 2.4) for v > 0.0031308
+  return v <= 0.0031308f ? 12.92f * v
+                         : 1.055f * __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(v) * (1.f / 2.4f)) - 0.055f;
 }
 __device__ inline float tonemap_eval(float L) {
-  return srgb(tau_eval(0.4f * logf(fmaxf(L, 0.f) + 1e-4f)));
+  return srgb(tau_eval(0.4f * fast_log(fmaxf(L, 0.f) + 1e-4f)));
 }
 
 // Bilinear sample of prev at (x + mv.x, y + mv.y), both taps clamped to the edge; the
@@ -485,17 +496,17 @@ __device__ inline void store_row<float>(float* dst, int C, const float* f) {
     d[5] = make_float4(f[20], f[21], f[22], f[23]);
   }
 }
+// bf16: the hardware packed conversion (round to nearest even, as f2bf for finite values)
+__device__ inline u16x8 pack_bf8(const float* f) {
+  const u16x4 lo = f2bf4(f[0], f[1], f[2], f[3]), hi = f2bf4(f[4], f[5], f[6], f[7]);
+  return u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
 template <>
 __device__ inline void store_row<uint16_t>(uint16_t* dst, int C, const float* f) {
   u16x8* d = reinterpret_cast<u16x8*>(dst);
-  d[0] = u16x8{f2bf(f[0]), f2bf(f[1]), f2bf(f[2]), f2bf(f[3]),
-               f2bf(f[4]), f2bf(f[5]), f2bf(f[6]), f2bf(f[7])};
-  if (C >= 16)
-    d[1] = u16x8{f2bf(f[8]), f2bf(f[9]), f2bf(f[10]), f2bf(f[11]),
-                 f2bf(f[12]), f2bf(f[13]), f2bf(f[14]), f2bf(f[15])};
-  if (C == 24)
-    d[2] = u16x8{f2bf(f[16]), f2bf(f[17]), f2bf(f[18]), f2bf(f[19]),
-                 f2bf(f[20]), f2bf(f[21]), f2bf(f[22]), f2bf(f[23])};
+  d[0] = pack_bf8(f);
+  if (C >= 16) d[1] = pack_bf8(f + 8);
+  if (C == 24) d[2] = pack_bf8(f + 16);
 }
 
 // kind 0 (sampler input):   aux[0..6], then (temporal) tonemap(W prev) 3, valid 1; zero pad.
@@ -526,9 +537,9 @@ __global__ __launch_bounds__(256) void k_features(int kind, const float* __restr
   int o = 7;
   if (kind == 1) {
     const float4 l = L0[i];
-    f[7] = slog1p(l.x);
-    f[8] = slog1p(l.y);
-    f[9] = slog1p(l.z);
+    f[7] = slog1p_fwd(l.x);
+    f[8] = slog1p_fwd(l.y);
+    f[9] = slog1p_fwd(l.z);
     f[10] = s[i];
     o = 11;
   }
@@ -540,9 +551,9 @@ __global__ __launch_bounds__(256) void k_features(int kind, const float* __restr
       f[o + 1] = tonemap_eval(w.y);
       f[o + 2] = tonemap_eval(w.z);
     } else {
-      f[o] = slog1p(w.x);
-      f[o + 1] = slog1p(w.y);
-      f[o + 2] = slog1p(w.z);
+      f[o] = slog1p_fwd(w.x);
+      f[o + 1] = slog1p_fwd(w.y);
+      f[o + 2] = slog1p_fwd(w.z);
     }
     f[o + 3] = mv_valid(H, W, x, y, m);
     if (lat) {
