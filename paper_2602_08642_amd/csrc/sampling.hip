@@ -78,10 +78,10 @@ __global__ __launch_bounds__(256) void k_norm_combine(const float2* __restrict__
   if (threadIdx.x == 0) stats[blockIdx.x] = ms;
 }
 
-// s = f*B + (1-f)*B*Npx * exp(z - max) / sum over kNormApply pixels per block (4 per thread);
+// s = f*B + (1-f)*B*Npx * exp(z - max) / sum over kNormApply pixels per block (8 per thread);
 // each block combines the image's partials itself (a few thousand L2-resident values) instead
 // of waiting for a combine launch.
-constexpr int kNormPer = 4, kNormApply = 256 * kNormPer;
+constexpr int kNormPer = 8, kNormApply = 256 * kNormPer;
 __global__ __launch_bounds__(256) void k_norm_apply(const float* __restrict__ z, int npx,
                                                     const float2* __restrict__ part, int nbp,
                                                     float c0, float c1, int vec,
