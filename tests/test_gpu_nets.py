@@ -112,7 +112,7 @@ def test_sampler_cnn_matches_oracle(ops, cin, dtype):
 
 @pytest.mark.parametrize("cin", [8, 16])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-@pytest.mark.parametrize("H,W", [(40, 56), (23, 37), (1, 5)])
+@pytest.mark.parametrize("H,W", [(40, 56), (23, 37), (1, 5), (16, 52), (67, 131)])
 def test_fused_sampler_equals_layer_by_layer(ops, cin, dtype, H, W):
     """The one-kernel sampler CNN gives the layer-by-layer result, including ragged bands and
     one-row images.  Both round the intermediates to the storage type, but they sum K in other
