@@ -1387,27 +1387,40 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     }
 }
 
+// The splits of 32 consecutive dW entries per block: split lane r = t / 32 (8 lanes) sums the
+// splits k = r, r + 8, ... in order into two accumulators (k / 8 even and odd), then lane 0 of
+// each entry adds the eight lane sums in lane order: a fixed order, eight times the
+// parallelism of one thread per entry.
+constexpr int kRedLanes = 8;
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int splits,
                                                       int Cout, int KK, int Cin, int CoutP,
                                                       int CinP, float* __restrict__ dw) {
-  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (size_t)Cout * KK * Cin) return;
-  const int ci = (int)(i % Cin);
-  const int tap = (int)((i / Cin) % KK);
-  const int co = (int)(i / ((size_t)Cin * KK));
-  // four accumulators over the splits k = j mod 4 (independent loads in flight), fixed order
-  const size_t stride = (size_t)CoutP * KK * CinP;
-  const float* pp = part + ((size_t)co * KK + tap) * CinP + ci;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  int k = 0;
-  for (; k + 3 < splits; k += 4) {
-    s0 += pp[(size_t)k * stride];
-    s1 += pp[(size_t)(k + 1) * stride];
-    s2 += pp[(size_t)(k + 2) * stride];
-    s3 += pp[(size_t)(k + 3) * stride];
+  __shared__ float red[kRedLanes][32];
+  const int t = threadIdx.x, e = t & 31, r = t >> 5;
+  const size_t i = (size_t)blockIdx.x * 32 + e;
+  const bool ok = i < (size_t)Cout * KK * Cin;
+  float s0 = 0.f, s1 = 0.f;
+  if (ok) {
+    const int ci = (int)(i % Cin);
+    const int tap = (int)((i / Cin) % KK);
+    const int co = (int)(i / ((size_t)Cin * KK));
+    const size_t stride = (size_t)CoutP * KK * CinP;
+    const float* pp = part + ((size_t)co * KK + tap) * CinP + ci;
+    int k = r;
+    for (; k + kRedLanes < splits; k += 2 * kRedLanes) {
+      s0 += pp[(size_t)k * stride];
+      s1 += pp[(size_t)(k + kRedLanes) * stride];
+    }
+    if (k < splits) s0 += pp[(size_t)k * stride];
   }
-  for (; k < splits; ++k) s0 += pp[(size_t)k * stride];
-  dw[i] = (s0 + s1) + (s2 + s3);
+  red[r][e] = s0 + s1;
+  __syncthreads();
+  if (r == 0 && ok) {
+    float v = 0.f;
+#pragma unroll
+    for (int q = 0; q < kRedLanes; ++q) v += red[q][e];
+    dw[i] = v;
+  }
 }
 
 // db[co] = sum_px dY[px][co] (masked), deterministic: block b sums the pixels [b per, (b+1) per).
@@ -1730,7 +1743,7 @@ int aps_conv2d_bwd_weight(const void* x, const void* x2, int mode, int N, int H,
     return APS_ERR_UNSUPPORTED;
   }
   const size_t nw = (size_t)Cout * ksize * ksize * Cin;
-  k_wgrad_reduce<<<(unsigned)((nw + 255) / 256), 256, 0, st>>>(a.part, p.splits, Cout,
+  k_wgrad_reduce<<<(unsigned)((nw + 31) / 32), 256, 0, st>>>(a.part, p.splits, Cout,
                                                                 ksize * ksize, Cin, p.CoutP, p.CinP,
                                                                 dw);
   if (db) {
