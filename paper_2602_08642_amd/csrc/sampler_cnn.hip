@@ -1,4 +1,5 @@
-// The density (sampler) CNN of Sec. 4 as one kernel: three 3x3 'same' convolutions, Cin -> 16
+// The density (sampler) CNN (Sec. 3, overview; Sec. 6.3) as one kernel: three 3x3 'same'
+// convolutions, Cin -> 16
 // (ReLU), 16 -> 16 (ReLU), 16 -> 1, with the two intermediates kept on chip, rounded to the
 // storage type and zero outside the image as the layer-by-layer path stores them.  Weights come
 // in the packed (tap, 8-channel group) pair order of the convolution kernels.  bf16 runs the
@@ -26,8 +27,8 @@ struct SamplerArgs {
 // with the LDS bank-conflict counter on gfx950, this keeps the B-operand reads (16 pixels x 2
 // groups x 2 shifts per instruction) conflict-free and the 8-byte C-fragment writes at the
 // cycles of a plain 8-byte store, where swapping on bit 3, or a 48-byte pitch, costs the reads
-// a quarter more cycles and no swizzle doubles the writes.  Otherwise (fp32, or bf16 with 8
-// channels) a padded pixel stride with the groups in order.
+// a quarter more cycles and no swizzle doubles the writes.  Otherwise the groups in order at a
+// pixel stride of 8 elements (bf16 with 8 channels) or 8 NG + 4 floats (fp32, padded).
 template <typename T, int NG>
 struct SLay {
   static constexpr bool kSw = sizeof(T) == 2 && NG == 2;
