@@ -1,9 +1,8 @@
 // The density (sampler) CNN (Sec. 3, overview; Sec. 6.3) as one kernel: three 3x3 'same'
-// convolutions, Cin -> 16
-// (ReLU), 16 -> 16 (ReLU), 16 -> 1, with the two intermediates kept on chip, rounded to the
-// storage type and zero outside the image as the layer-by-layer path stores them.  Weights come
-// in the packed (tap, 8-channel group) pair order of the convolution kernels.  bf16 runs the
-// row-sweep form (k_sampler_sweep), fp32 the tiled form (k_sampler_cnn).
+// convolutions, Cin -> 16 (ReLU), 16 -> 16 (ReLU), 16 -> 1, with the two intermediates kept on
+// chip, rounded to the storage type and zero outside the image as the layer-by-layer path
+// stores them.  Weights come in the packed (tap, 8-channel group) pair order of the convolution
+// kernels.  bf16 runs the row-sweep form (k_sampler_sweep), fp32 the tiled form (k_sampler_cnn).
 #include <algorithm>
 #include <type_traits>
 
