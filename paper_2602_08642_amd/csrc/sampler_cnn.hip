@@ -21,23 +21,46 @@ struct SamplerArgs {
   float* z;
 };
 
-// LDS layout of a pixel's 8-channel groups.  bf16 with 16 channels: 32-byte pixels whose two
-// 16-byte halves swap on every other run of 4 pixels (an XOR swizzle on pixel bit 2).  Measured
-// with the LDS bank-conflict counter on gfx950, this keeps the B-operand reads (16 pixels x 2
-// groups x 2 shifts per instruction) conflict-free and the 8-byte C-fragment writes at the
-// cycles of a plain 8-byte store, where swapping on bit 3, or a 48-byte pitch, costs the reads
-// a quarter more cycles and no swizzle doubles the writes.  Otherwise the groups in order at a
-// pixel stride of 8 elements (bf16 with 8 channels) or 8 NG + 4 floats (fp32, padded).
+// LDS layouts of a pixel's channels, in 16-byte chunks (8 bf16 or 4 floats).  The layouts were
+// chosen with the LDS bank-conflict counter on gfx950 (probe kernels of each access shape).
+// bf16, 16 channels: 32-byte pixels whose two chunks swap on every other run of 4 pixels (an XOR
+// swizzle on pixel bit 2): the B-operand reads (16 pixels x 2 chunks x 2 shifts per
+// instruction) are conflict-free and the 8-byte C-fragment writes take the cycles of a plain
+// 8-byte store, where swapping on bit 3, or a 48-byte pitch, costs the reads a quarter more
+// cycles and no swizzle doubles the writes.  fp32, 16 channels: 64-byte pixels whose chunk c
+// sits at c ^ ((p >> 1) & 3): the 16-byte C-fragment writes (lane group q writes chunk q of 16
+// consecutive pixels) take 8 cycles, as with an 80-byte pitch, against 16-32 unswizzled, and
+// the group reads are unchanged (so a block needs 20 % less LDS: three blocks per CU).  8
+// channels: the chunks in order at a 16-byte (bf16) or 32-byte (fp32) pixel stride.
 template <typename T, int NG>
 struct SLay {
-  static constexpr bool kSw = sizeof(T) == 2 && NG == 2;
-  static constexpr int kPs = kSw ? 16 : (sizeof(T) == 2 ? 8 : 8 * NG + 4);  // elements per pixel
-  static __device__ inline int at(int p, int g) {
-    if constexpr (kSw) return p * 16 + ((g ^ ((p >> 2) & 1)) << 3);
-    else return p * kPs + g * 8;
+  static constexpr int kPs = 8 * NG;  // elements per pixel
+  static constexpr int kCh = 16 / sizeof(T);  // elements per chunk
+  static __device__ inline int chunk(int p, int c) {  // element offset of chunk c of pixel p
+    if constexpr (NG == 2 && sizeof(T) == 2) return p * 16 + ((c ^ ((p >> 2) & 1)) << 3);
+    else if constexpr (NG == 2) return p * 16 + ((c ^ ((p >> 1) & 3)) << 2);
+    else return p * kPs + c * kCh;
+  }
+  // element offset of 8-channel group g (bf16: one chunk; fp32: its first chunk, see group_load)
+  static __device__ inline int at(int p, int g) { return chunk(p, g * (8 / kCh)); }
+  // the 4-channel slice c4 (channels 4 c4 .. 4 c4 + 3)
+  static __device__ inline int quad(int p, int c4) {
+    if constexpr (sizeof(T) == 2) return chunk(p, c4 >> 1) + 4 * (c4 & 1);
+    else return chunk(p, c4);
   }
 };
-
+// 8 channels of group g of pixel p as an MFMA fragment (fp32: two chunks, wherever they sit)
+template <int NG>
+__device__ inline void group_load(Frag<uint16_t>& f, const uint16_t* X, int p, int g) {
+  frag_load(f, X + SLay<uint16_t, NG>::at(p, g));
+}
+template <int NG>
+__device__ inline void group_load(Frag<float>& f, const float* X, int p, int g) {
+  const float4 a = *reinterpret_cast<const float4*>(X + SLay<float, NG>::chunk(p, 2 * g));
+  const float4 b = *reinterpret_cast<const float4*>(X + SLay<float, NG>::chunk(p, 2 * g + 1));
+  f.v[0] = a.x; f.v[1] = a.y; f.v[2] = a.z; f.v[3] = a.w;
+  f.v[4] = b.x; f.v[5] = b.y; f.v[6] = b.z; f.v[7] = b.w;
+}
 // One hidden layer (16 outputs, ReLU) on MFMA: output grid WOUT x WOUT at image (oy, ox), input
 // grid WIN x WIN in LDS (layout SLay<T, CG>), output to Y (layout SLay<T, 2>).
 template <typename T, int CG, int WIN, int WOUT>
@@ -67,7 +90,7 @@ __device__ inline void sampler_hidden(const T* Xin, T* Y, const T* wp, const flo
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) {
       Frag<T> bf;
-      frag_load(bf, Xin + LI::at(p0 + toff[s], grp[s]));
+      group_load<CG>(bf, Xin, p0 + toff[s], grp[s]);
       acc = mma(wf[s], bf, acc);
     }
     if (valid) {
@@ -76,7 +99,7 @@ __device__ inline void sampler_hidden(const T* Xin, T* Y, const T* wp, const flo
       float v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) v[q] = inside ? fmaxf(acc[q] + b[q], 0.f) : 0.f;
-      T* d = Y + LO::at(pix, co >> 3) + (co & 7);
+      T* d = Y + LO::quad(pix, co >> 2);
       if constexpr (sizeof(T) == 2) *reinterpret_cast<u16x4*>(d) = f2bf4(v[0], v[1], v[2], v[3]);
       else *reinterpret_cast<float4*>(d) = make_float4(v[0], v[1], v[2], v[3]);
     }
@@ -103,11 +126,16 @@ __global__ __launch_bounds__(256) void k_sampler_cnn(SamplerArgs a) {
   for (int it = tid; it < 22 * 22 * CG0; it += 256) {
     const int g = it % CG0, p = it / CG0, r = p / 22, c = p - r * 22;
     const int iy = ty0 - 3 + r, ix = tx0 - 3 + c;
-    T* d = X0 + L0::at(p, g);
-    if (iy >= 0 && iy < a.H && ix >= 0 && ix < a.W)
-      copy8(d, x + (((size_t)n * a.H + iy) * a.W + ix) * a.C + g * 8);
-    else
-      zero8(d);
+    float* d0 = X0 + L0::chunk(p, 2 * g);
+    float* d1 = X0 + L0::chunk(p, 2 * g + 1);
+    float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
+    if (iy >= 0 && iy < a.H && ix >= 0 && ix < a.W) {
+      const float4* src = reinterpret_cast<const float4*>(x + (((size_t)n * a.H + iy) * a.W + ix) * a.C + g * 8);
+      v0 = src[0];
+      v1 = src[1];
+    }
+    *reinterpret_cast<float4*>(d0) = v0;
+    *reinterpret_cast<float4*>(d1) = v1;
   }
   __syncthreads();
   sampler_hidden<T, CG0, 22, 20>(X0, H1, static_cast<const T*>(a.w[0]), a.b[0], a.H, a.W, ty0 - 2,
@@ -126,11 +154,14 @@ __global__ __launch_bounds__(256) void k_sampler_cnn(SamplerArgs a) {
     const int pp = (r + tap / 3) * 18 + c + tap % 3;
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
-      const float* px = X0 + L1::at(pp, g);
       const int pr = 2 * tap + g;
       const float* wv = wp2 + ((pr / 4) * 64 + 16 * (pr % 4)) * 8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) acc = fmaf(wv[e], px[e], acc);
+      for (int h = 0; h < 2; ++h) {
+        const float* px = X0 + L1::chunk(pp, 2 * g + h);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = fmaf(wv[4 * h + e], px[e], acc);
+      }
     }
   }
   const int iy = ty0 + r, ix = tx0 + c;
