@@ -7,6 +7,9 @@
 // Input transforms fused into the staging: 2x2 average pool of a finer tensor, or nearest
 // 2x upsampling of a coarser tensor concatenated with a skip tensor (U-Net decoder).
 // Epilogue: bias, optional ReLU, store (f32 or bf16).
+#include <algorithm>
+#include <type_traits>
+
 #include "aps_common.h"
 #include "mfma_frag.h"
 
@@ -928,6 +931,206 @@ void launch_conv_lds_m(const ConvArgs& a, hipStream_t st) {
   }
 }
 
+// ---- bf16 3x3 convolution with 32 output channels as a per-wave row sweep ----------------
+// For the full-resolution 32-channel layers (16 or 32 input channels), which move far more bytes
+// than they compute: the tiled blocks stage a tile and its weights, compute for a fraction of the
+// time and store, with too little work per block to hide the staging behind the other blocks of
+// a CU.  Here each wave runs on its own, with no block barrier: it owns a band of 32 output
+// columns and R output rows, keeps its weights in registers, and walks down the band one output
+// row per step, reading each input row from HBM once (requested kCsDepth steps before it is staged, through
+// a buffer resource whose out-of-image lanes return zeros) into a ring of four LDS rows.  Output row o is
+// summed from input rows o - 1, o, o + 1 in the tiled kernel's order — taps dx outer, dy inner,
+// one MFMA per tap over the 32 channels of the chunk (zeros above 16 input channels), starting
+// from the bias — so the two kernels agree bit for bit and either may serve a layer.  The row is
+// rounded to bf16, rectified on the rounded bits, staged in LDS and stored as 16-byte runs; with a
+// pooled output every second row is averaged with the one before it in the order of the POOL2
+// input transform.  LDS operations of one wave complete in program order, so no barrier orders
+// the ring or the staging rows.
+constexpr int kCsCols = 32;      // output columns per band (two 16-pixel n-tiles)
+constexpr int kCsPix = 36;       // staged input positions per row: 34 read + 2 zero (pad reads)
+constexpr long kCsWaves = 2048;  // waves per launch the band height aims at (two per SIMD)
+constexpr int kCsDepth = 4;      // input rows requested ahead (the band height is a multiple)
+
+// element offset of 8-channel group g of staged pixel p (CG groups per pixel): 64-byte pixels
+// swizzle their chunks on pixel bits 1-2, 32-byte pixels on bit 2
+template <int CG>
+__device__ inline int cs_off(int p, int g) {
+  if constexpr (CG == 4) return p * 32 + ((g ^ ((p >> 1) & 3)) << 3);
+  else return p * 16 + ((g ^ ((p >> 2) & 1)) << 3);
+}
+
+template <int CG>
+__global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg, int nunit) {
+  using T = uint16_t;
+  constexpr int XR = kCsPix * CG * 8;          // elements of one ring row
+  constexpr int XN = 4 * XR, ON = 2 * kCsCols * 32;
+  constexpr int NLD = (34 * CG + 63) / 64;     // 16-byte input loads per lane and row
+  constexpr int D = kCsDepth;                  // input rows in flight in registers
+  __shared__ __attribute__((aligned(16))) T lds[4][XN + ON];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int unit = blockIdx.x * 4 + wave, n = blockIdx.y;
+  if (unit >= nunit) return;  // the whole wave; nothing below synchronises waves
+  const int H = a.H, W = a.W;
+  const int x0 = (unit / nseg) * kCsCols, y0 = (unit % nseg) * R;
+  T* X = lds[wave];
+  T* O = X + XN;  // two output rows, [2][32 px][32 channels], chunks swizzled as cs_off<4>
+  for (int e = lane * 8; e < XN + ON; e += 512) zero8(X + e);
+
+  // weights of the chunk layout: fragment (m, tap), lane l = output channel 16 m + l % 16,
+  // input channels 8 (l / 16) .. + 7
+  const T* wp = static_cast<const T*>(a.wp);
+  Frag<T> w[2][9];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) frag_load(w[m][t], wp + ((size_t)(m * 9 + t) * 64 + lane) * 8);
+  f32x4 bias[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) bias[m] = *reinterpret_cast<const f32x4*>(a.bias + 16 * m + 4 * (lane >> 4));
+  // this lane's B operand offset within a ring row (n-tile s, tap column dx); groups beyond the
+  // input channels read the zero pad
+  int bo[2][3];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+      bo[s][dx] = (lane >> 4) < CG ? cs_off<CG>(16 * s + (lane & 15) + dx, lane >> 4) : cs_off<CG>(34, 0);
+  // input rows: chunk c = lane + 64 k of the row is pixel c / CG (column x0 - 1 + c / CG), group c % CG
+  const uint32_t img_bytes = (uint32_t)((size_t)H * W * a.Cx * sizeof(T));
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<T*>(static_cast<const T*>(a.x) + (size_t)n * H * W * a.Cx), 0, img_bytes, 0x00020000);
+  auto load_row = [&](int iy, u16x8 (&v)[NLD]) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int c = lane + 64 * k, px = c / CG, g = c % CG, xc = x0 - 1 + px;
+      const bool in = c < 34 * CG && iy >= 0 && iy < H && xc >= 0 && xc < W;
+      const uint32_t off = in ? (uint32_t)((((size_t)iy * W + xc) * a.Cx + g * 8) * sizeof(T)) : img_bytes;
+      v[k] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+    }
+  };
+  auto store_row = [&](T* dst, const u16x8 (&v)[NLD]) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int c = lane + 64 * k;
+      if (c < 34 * CG) *reinterpret_cast<u16x8*>(dst + cs_off<CG>(c / CG, c % CG)) = v[k];
+    }
+  };
+  T* y = static_cast<T*>(a.y);
+  T* yp = static_cast<T*>(a.pool);
+  const int ylast = min(y0 + R, H) - 1;
+  // emission of output row o from the accumulators acc[s][m]
+  auto emit = [&](const f32x4 (&acc)[2][2], int o) {
+    T* Ob = O + (o & 1) * (kCsCols * 32);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        s16x4 h = __builtin_bit_cast(s16x4, f2bf4(acc[s][m][0], acc[s][m][1], acc[s][m][2], acc[s][m][3]));
+        if (a.relu) h = __builtin_elementwise_max(h, s16x4{0, 0, 0, 0});
+        const int px = 16 * s + (lane & 15), co = 16 * m + 4 * (lane >> 4);
+        *reinterpret_cast<s16x4*>(Ob + cs_off<4>(px, co >> 3) + (co & 7)) = h;
+      }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // other lanes' staged values are read below
+    const size_t rowbase = ((size_t)n * H + o) * W;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int q = lane + 64 * k, px = q >> 2, g = q & 3;
+      if (x0 + px < W)
+        *reinterpret_cast<u16x8*>(y + (rowbase + x0 + px) * a.ldy + 8 * g) =
+            *reinterpret_cast<const u16x8*>(Ob + cs_off<4>(px, g));
+    }
+    if (yp && ((o - y0) & 1)) {  // rows o - 1 and o: the 2x2 means of 16 pooled pixels
+      const T* Oa = O + ((o - 1) & 1) * (kCsCols * 32);
+      const int xp = lane >> 2, g = lane & 3;
+      if (x0 + 2 * xp < W) {
+        const u16x8 a0 = *reinterpret_cast<const u16x8*>(Oa + cs_off<4>(2 * xp, g));
+        const u16x8 a1 = *reinterpret_cast<const u16x8*>(Oa + cs_off<4>(2 * xp + 1, g));
+        const u16x8 b0 = *reinterpret_cast<const u16x8*>(Ob + cs_off<4>(2 * xp, g));
+        const u16x8 b1 = *reinterpret_cast<const u16x8*>(Ob + cs_off<4>(2 * xp + 1, g));
+        float r[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          r[e] = ((bf2f(a0[e]) + bf2f(a1[e])) + (bf2f(b0[e]) + bf2f(b1[e]))) * 0.25f;
+        const u16x4 lo = f2bf4(r[0], r[1], r[2], r[3]), hi = f2bf4(r[4], r[5], r[6], r[7]);
+        *reinterpret_cast<u16x8*>(yp + (((size_t)n * (H / 2) + o / 2) * (W / 2) + (x0 / 2 + xp)) * a.Cout + 8 * g) =
+            u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+    }
+  };
+
+  // ring row k (k = input row - (y0 - 1)) sits in slot k % 4; rows 0..2 are staged up front and
+  // rows 3..2 + D wait in registers gx[k % D]
+  {
+    u16x8 v[NLD];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      load_row(y0 - 1 + k, v);
+      store_row(X + k * XR, v);
+    }
+  }
+  u16x8 gx[D][NLD];
+#pragma unroll
+  for (int k = 3; k < 3 + D; ++k) load_row(y0 - 1 + k, gx[k % D]);
+
+  // step i: output row y0 + i from ring rows i, i + 1, i + 2; then ring row i + 3 is staged
+  // (its slot held row i - 1, read by the previous step) and row i + 3 + D is requested
+  auto step = [&](auto ph, int i) {
+    constexpr int G = (decltype(ph)::value + 3) % D;  // == (i + 3) % D
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) acc[s][m] = bias[m];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      __builtin_amdgcn_sched_barrier(0);  // one tap column's operands live at a time
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const T* row = X + ((i + dy) & 3) * XR;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          Frag<T> b;
+          frag_load(b, row + bo[s][dx]);
+#pragma unroll
+          for (int m = 0; m < 2; ++m) acc[s][m] = mma(w[m][3 * dy + dx], b, acc[s][m]);
+        }
+      }
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const int o = y0 + i;
+    if (o <= ylast) emit(acc, o);
+    store_row(X + ((i + 3) & 3) * XR, gx[G]);
+    load_row(y0 + 2 + i + D, gx[G]);
+  };
+  for (int i = 0; i < R; i += D) {  // R % D == 0 (host)
+    step(std::integral_constant<int, 0>{}, i);
+    step(std::integral_constant<int, 1>{}, i + 1);
+    step(std::integral_constant<int, 2>{}, i + 2);
+    step(std::integral_constant<int, 3>{}, i + 3);
+  }
+}
+
+// false: not this kernel's configuration (bf16 3x3 direct, 32 outputs, 16 or 32 inputs, no head)
+bool launch_conv_sweep(const ConvArgs& a, hipStream_t st) {
+  if (a.mode != APS_CONV_DIRECT || a.C2 != 0 || a.Cout != 32 || a.ldy != 32 || a.hw || a.hside ||
+      a.nchunk != 1 || (a.Cx != 16 && a.Cx != 32) || !a.bias)
+    return false;
+  if (a.pool && (a.H % 2 || a.W % 2)) return false;
+  if ((size_t)a.H * a.W * a.Cx * 2 >= (1ull << 31) || a.N > 65535) return false;
+  const long nband = (a.W + kCsCols - 1) / kCsCols;
+  // rows per wave: a multiple of the prefetch depth (even, so pooled rows pair up in a segment)
+  long R = std::max<long>(8, ((long)a.N * a.H * nband + kCsWaves - 1) / kCsWaves);
+  R = (std::min<long>(R, a.H) + kCsDepth - 1) / kCsDepth * kCsDepth;
+  const int nseg = (int)((a.H + R - 1) / R);
+  const long nunit = nband * nseg;
+  if (nunit > (1L << 30) / 4) return false;
+  dim3 g((unsigned)((nunit + 3) / 4), a.N);
+  if (a.Cx == 32) k_conv_sweep<4><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  else k_conv_sweep<2><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  return true;
+}
+
 // false: the configuration is not covered (the caller uses k_conv)
 template <int HEAD>
 bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
@@ -943,6 +1146,7 @@ bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
     launch_conv_lds_m<APS_CONV_DIRECT, HEAD>(a, st);
     return true;
   } else {
+    if (launch_conv_sweep(a, st)) return true;
     switch (a.mode) {
       case APS_CONV_DIRECT: launch_conv_lds_m<APS_CONV_DIRECT, 0>(a, st); return true;
       case APS_CONV_POOL2: launch_conv_lds_m<APS_CONV_POOL2, 0>(a, st); return true;
