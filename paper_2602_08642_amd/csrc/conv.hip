@@ -937,19 +937,31 @@ void launch_conv_lds_m(const ConvArgs& a, hipStream_t st) {
 // time and store, with too little work per block to hide the staging behind the other blocks of
 // a CU.  Here each wave runs on its own, with no block barrier: it owns a band of 32 output
 // columns and R output rows, keeps its weights in registers, and walks down the band one output
-// row per step, reading each input row from HBM once (requested kCsDepth steps before it is staged, through
-// a buffer resource whose out-of-image lanes return zeros) into a ring of four LDS rows.  Output row o is
-// summed from input rows o - 1, o, o + 1 in the tiled kernel's order — taps dx outer, dy inner,
-// one MFMA per tap over the 32 channels of the chunk (zeros above 16 input channels), starting
-// from the bias — so the two kernels agree bit for bit and either may serve a layer.  The row is
-// rounded to bf16, rectified on the rounded bits, staged in LDS and stored as 16-byte runs; with a
-// pooled output every second row is averaged with the one before it in the order of the POOL2
-// input transform.  LDS operations of one wave complete in program order, so no barrier orders
-// the ring or the staging rows.
+// row per step, reading each input row from HBM once (requested four steps before it is staged,
+// two with a fused head, through a buffer resource whose out-of-image lanes return zeros) into a
+// ring of four LDS rows.  Output row o is summed from input rows o - 1, o, o + 1 in the tiled
+// kernel's order — taps dx outer, dy inner, one MFMA per tap over the 32 channels of the chunk
+// (zeros above 16 input channels), starting from the bias — so the two kernels agree bit for bit
+// and either may serve a layer.  The row is rounded to bf16, rectified on the rounded bits,
+// staged in LDS and stored as 16-byte runs; with a pooled output every second row is averaged
+// with the one before it in the order of the POOL2 input transform; with a fused 1x1 head (HM
+// m-tiles of logits) the staged row is the head's B operand, as in the tiled epilogue.  LDS
+// operations of one wave complete in program order, so no block barrier orders the ring or the
+// staging rows; wave_lds_sync keeps the compiler from reordering them.
 constexpr int kCsCols = 32;      // output columns per band (two 16-pixel n-tiles)
 constexpr int kCsPix = 36;       // staged input positions per row: 34 read + 2 zero (pad reads)
 constexpr long kCsWaves = 2048;  // waves per launch the band height aims at (two per SIMD)
-constexpr int kCsDepth = 4;      // input rows requested ahead (the band height is a multiple)
+constexpr int kCsDepth = 4;      // input rows requested ahead, steps per loop iteration (R % 4 == 0)
+
+// Orders this wave's LDS accesses across lanes: a compiler barrier for memory operations (the
+// LDS itself completes one wave's operations in program order).  Plain signal fences are not
+// enough where the two sides use different vector types, which type-based alias analysis may
+// then take as disjoint.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // element offset of 8-channel group g of staged pixel p (CG groups per pixel): 64-byte pixels
 // swizzle their chunks on pixel bits 1-2, 32-byte pixels on bit 2
@@ -959,14 +971,16 @@ __device__ inline int cs_off(int p, int g) {
   else return p * 16 + ((g ^ ((p >> 2) & 1)) << 3);
 }
 
-template <int CG>
+template <int CG, int HM>
 __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg, int nunit) {
   using T = uint16_t;
   constexpr int XR = kCsPix * CG * 8;          // elements of one ring row
   constexpr int XN = 4 * XR, ON = 2 * kCsCols * 32;
+  // a row's staged logits [32 px][hldy <= 16 HM], then the head biases as floats (16 HM)
+  constexpr int LN = HM ? kCsCols * 16 * HM + 32 * HM : 0;
   constexpr int NLD = (34 * CG + 63) / 64;     // 16-byte input loads per lane and row
-  constexpr int D = kCsDepth;                  // input rows in flight in registers
-  __shared__ __attribute__((aligned(16))) T lds[4][XN + ON];
+  constexpr int D = HM ? 2 : kCsDepth;         // input rows in flight in registers
+  __shared__ __attribute__((aligned(16))) T lds[4][XN + ON + LN];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int unit = blockIdx.x * 4 + wave, n = blockIdx.y;
   if (unit >= nunit) return;  // the whole wave; nothing below synchronises waves
@@ -974,6 +988,7 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
   const int x0 = (unit / nseg) * kCsCols, y0 = (unit % nseg) * R;
   T* X = lds[wave];
   T* O = X + XN;  // two output rows, [2][32 px][32 channels], chunks swizzled as cs_off<4>
+  T* Ls = O + ON;
   for (int e = lane * 8; e < XN + ON; e += 512) zero8(X + e);
 
   // weights of the chunk layout: fragment (m, tap), lane l = output channel 16 m + l % 16,
@@ -987,6 +1002,20 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
   f32x4 bias[2];
 #pragma unroll
   for (int m = 0; m < 2; ++m) bias[m] = *reinterpret_cast<const f32x4*>(a.bias + 16 * m + 4 * (lane >> 4));
+  // fused 1x1 head (HM m-tiles of logits): the packed head weights of the one 32-channel chunk
+  // and the head biases, as the tiled kernel's epilogue holds them
+  // (biases in LDS, read per row, to keep the weights and the row prefetch in registers)
+  Frag<T> hwf[HM ? HM : 1];
+  float* Hb = reinterpret_cast<float*>(Ls + kCsCols * 16 * HM);
+  if constexpr (HM != 0) {
+    const T* hw = static_cast<const T*>(a.hw);
+#pragma unroll
+    for (int mh = 0; mh < HM; ++mh) {
+      hwf[mh].v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (mh * 16 < a.hK) frag_load(hwf[mh], hw + ((size_t)mh * 64 + lane) * 8);
+    }
+    for (int k = lane; k < 16 * HM; k += 64) Hb[k] = k < a.hK ? a.hb[k] : 0.f;
+  }
   // this lane's B operand offset within a ring row (n-tile s, tap column dx); groups beyond the
   // input channels read the zero pad
   int bo[2][3];
@@ -1030,14 +1059,51 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
         const int px = 16 * s + (lane & 15), co = 16 * m + 4 * (lane >> 4);
         *reinterpret_cast<s16x4*>(Ob + cs_off<4>(px, co >> 3) + (co & 7)) = h;
       }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // other lanes' staged values are read below
+    wave_lds_sync();  // other lanes' staged values are read below
     const size_t rowbase = ((size_t)n * H + o) * W;
+    if (HM == 0 || a.store_main) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int q = lane + 64 * k, px = q >> 2, g = q & 3;
-      if (x0 + px < W)
-        *reinterpret_cast<u16x8*>(y + (rowbase + x0 + px) * a.ldy + 8 * g) =
-            *reinterpret_cast<const u16x8*>(Ob + cs_off<4>(px, g));
+      for (int k = 0; k < 2; ++k) {
+        const int q = lane + 64 * k, px = q >> 2, g = q & 3;
+        if (x0 + px < W)
+          *reinterpret_cast<u16x8*>(y + (rowbase + x0 + px) * a.ldy + 8 * g) =
+              *reinterpret_cast<const u16x8*>(Ob + cs_off<4>(px, g));
+      }
+    }
+    if constexpr (HM != 0) {
+      // the head on the staged (rounded, rectified) row: per 16-pixel n-tile one MFMA per head
+      // m-tile, from zero, then the head bias, as the tiled epilogue and the stand-alone 1x1
+      // convolution; logits staged as [px][hldy] (zeros in [hK, hldy)) and written as the row's
+      // contiguous run, nontemporal (read back only by the filter, after the other heads)
+      uint16_t* hy = static_cast<uint16_t*>(a.hy);
+      const int hldy = a.hldy, npx = min(kCsCols, W - x0);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        Frag<T> b;
+        frag_load(b, Ob + cs_off<4>(16 * s + (lane & 15), lane >> 4));
+#pragma unroll
+        for (int mh = 0; mh < HM; ++mh) {
+          if (mh * 16 >= hldy) break;
+          f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
+          if (mh * 16 < a.hK) h = mma(hwf[mh], b, h);
+          const int k0 = mh * 16 + 4 * (lane >> 4);
+          const f32x4 hb = *reinterpret_cast<const f32x4*>(Hb + k0);
+          float v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = k0 + q < a.hK ? h[q] + hb[q] : 0.f;
+          if (k0 < hldy) *reinterpret_cast<u16x4*>(Ls + (16 * s + (lane & 15)) * hldy + k0) = f2bf4(v[0], v[1], v[2], v[3]);
+        }
+      }
+      wave_lds_sync();
+      const int nvec = npx * hldy / 8;
+      u32x4* dst = reinterpret_cast<u32x4*>(hy + (rowbase + x0) * hldy);
+      for (int v = lane; v < nvec; v += 64)
+        __builtin_nontemporal_store(__builtin_bit_cast(u32x4, *reinterpret_cast<const u16x8*>(Ls + 8 * v)), dst + v);
+      if (a.hside && lane < npx) {
+        const uint16_t* op = Ls + lane * hldy + a.hside_off;
+        *reinterpret_cast<u16x4*>(static_cast<uint16_t*>(a.hside) + (rowbase + x0 + lane) * 4) =
+            u16x4{op[0], op[1], op[2], (uint16_t)0};
+      }
     }
     if (yp && ((o - y0) & 1)) {  // rows o - 1 and o: the 2x2 means of 16 pooled pixels
       const T* Oa = O + ((o - 1) & 1) * (kCsCols * 32);
@@ -1076,7 +1142,7 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
   // (its slot held row i - 1, read by the previous step) and row i + 3 + D is requested
   auto step = [&](auto ph, int i) {
     constexpr int G = (decltype(ph)::value + 3) % D;  // == (i + 3) % D
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_lds_sync();
     f32x4 acc[2][2];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
@@ -1097,13 +1163,14 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
         }
       }
     }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_lds_sync();
     const int o = y0 + i;
     if (o <= ylast) emit(acc, o);
     store_row(X + ((i + 3) & 3) * XR, gx[G]);
     load_row(y0 + 2 + i + D, gx[G]);
   };
-  for (int i = 0; i < R; i += D) {  // R % D == 0 (host)
+  static_assert(kCsDepth == 4 && 4 % D == 0, "four steps per iteration cycle the ring and gx");
+  for (int i = 0; i < R; i += 4) {  // R % 4 == 0 (host)
     step(std::integral_constant<int, 0>{}, i);
     step(std::integral_constant<int, 1>{}, i + 1);
     step(std::integral_constant<int, 2>{}, i + 2);
@@ -1111,12 +1178,22 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
   }
 }
 
-// false: not this kernel's configuration (bf16 3x3 direct, 32 outputs, 16 or 32 inputs, no head)
+// false: not this kernel's configuration: bf16 3x3 direct, 32 outputs, 16 or 32 inputs; with
+// HM, the fused head (32 inputs, logits staged: kstride <= 16 HM, 16-byte rows and base), no pool
+template <int HM>
 bool launch_conv_sweep(const ConvArgs& a, hipStream_t st) {
-  if (a.mode != APS_CONV_DIRECT || a.C2 != 0 || a.Cout != 32 || a.ldy != 32 || a.hw || a.hside ||
-      a.nchunk != 1 || (a.Cx != 16 && a.Cx != 32) || !a.bias)
+  if (a.mode != APS_CONV_DIRECT || a.C2 != 0 || a.Cout != 32 || a.nchunk != 1 || !a.bias ||
+      (a.Cx != 16 && a.Cx != 32))
     return false;
-  if (a.pool && (a.H % 2 || a.W % 2)) return false;
+  if constexpr (HM == 0) {
+    if (a.hw || a.hside || a.ldy != 32) return false;
+    if (a.pool && (a.H % 2 || a.W % 2)) return false;
+  } else {
+    if (a.Cx != 32 || a.pool || !a.hw || !a.hb || !a.hy || a.hK > 16 * HM || a.hldy > 16 * HM ||
+        (a.hldy * 2) % 16 || (reinterpret_cast<uintptr_t>(a.hy) & 15) ||
+        (a.hside && (reinterpret_cast<uintptr_t>(a.hside) & 7)) || (a.store_main && a.ldy != 32))
+      return false;
+  }
   if ((size_t)a.H * a.W * a.Cx * 2 >= (1ull << 31) || a.N > 65535) return false;
   const long nband = (a.W + kCsCols - 1) / kCsCols;
   // rows per wave: a multiple of the prefetch depth (even, so pooled rows pair up in a segment)
@@ -1126,8 +1203,8 @@ bool launch_conv_sweep(const ConvArgs& a, hipStream_t st) {
   const long nunit = nband * nseg;
   if (nunit > (1L << 30) / 4) return false;
   dim3 g((unsigned)((nunit + 3) / 4), a.N);
-  if (a.Cx == 32) k_conv_sweep<4><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
-  else k_conv_sweep<2><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  if (a.Cx == 32) k_conv_sweep<4, HM><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  else if constexpr (HM == 0) k_conv_sweep<2, 0><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
   return true;
 }
 
@@ -1143,10 +1220,11 @@ bool launch_conv_lds(const ConvArgs& a, hipStream_t st) {
   if ((ex > e2 ? ex : e2) + kChunk >= ((size_t)1 << 31)) return false;
   if constexpr (HEAD) {
     if (a.mode != APS_CONV_DIRECT) return false;
+    if (launch_conv_sweep<HEAD>(a, st)) return true;
     launch_conv_lds_m<APS_CONV_DIRECT, HEAD>(a, st);
     return true;
   } else {
-    if (launch_conv_sweep(a, st)) return true;
+    if (launch_conv_sweep<0>(a, st)) return true;
     switch (a.mode) {
       case APS_CONV_DIRECT: launch_conv_lds_m<APS_CONV_DIRECT, 0>(a, st); return true;
       case APS_CONV_POOL2: launch_conv_lds_m<APS_CONV_POOL2, 0>(a, st); return true;
