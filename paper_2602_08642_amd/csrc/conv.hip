@@ -888,6 +888,8 @@ void launch_conv_lds_f32_m(const ConvArgs& a, hipStream_t st) {
 
 // Every fp32 3x3 convolution with more than 16 input channels (its weights are packed in
 // 16-channel chunks, which only this kernel reads).  false: 32-bit offsets would overflow.
+bool launch_conv_sweep_f32(const ConvArgs& a, hipStream_t st);  // the row sweep, below
+
 template <int HEAD>
 bool launch_conv_lds_f32(const ConvArgs& a, hipStream_t st) {
   const size_t px = (size_t)a.N * a.H * a.W;
@@ -900,6 +902,7 @@ bool launch_conv_lds_f32(const ConvArgs& a, hipStream_t st) {
     launch_conv_lds_f32_m<APS_CONV_DIRECT, HEAD>(a, st);
     return true;
   } else {
+    if (launch_conv_sweep_f32(a, st)) return true;
     switch (a.mode) {
       case APS_CONV_DIRECT: launch_conv_lds_f32_m<APS_CONV_DIRECT, 0>(a, st); return true;
       case APS_CONV_POOL2: launch_conv_lds_f32_m<APS_CONV_POOL2, 0>(a, st); return true;
@@ -1205,6 +1208,197 @@ bool launch_conv_sweep(const ConvArgs& a, hipStream_t st) {
   dim3 g((unsigned)((nunit + 3) / 4), a.N);
   if (a.Cx == 32) k_conv_sweep<4, HM><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
   else if constexpr (HM == 0) k_conv_sweep<2, 0><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  return true;
+}
+
+// ---- fp32 form of the row sweep ------------------------------------------------------------
+// The same per-wave sweep for the fp32 networks' 32-channel full-resolution layers (16 or 32
+// input channels, 32 outputs, no head): on the tiled fp32 kernel these run at 57-68 % of the
+// MFMA peak against 81-87 % for the wider layers, each block computing two 16-channel chunks at
+// most for one staged tile.  Here the weights (2 m-tiles x 9 taps x CH chunks of 16 channels) stay
+// in registers and each input row is read from HBM once per band into a ring of three LDS rows,
+// each held as CH planes of [36 px][20 floats] (the tiled kernel's 80-byte pixel pitch, so the
+// 16 lanes of a B read hit distinct banks).  Output row o is summed in the tiled kernel's order:
+// 16-channel chunks outer, then taps dx, dy, four K = 4 MFMAs per tap, from the bias; so the two
+// kernels give the same bits.  Epilogue as lds_epilogue_f32: ReLU, 16-byte stores per lane, and
+// with a pooled output the 2x2 mean of the previous and the current row (neighbour column by DPP)
+// in the POOL2 order.  Ring row i + 3 is staged into the slot of row i after this step's reads of
+// it (one wave's LDS operations complete in program order).
+constexpr int kCsfPS = 20;       // floats per staged pixel of a 16-channel plane
+
+template <int CH, int MS>
+__global__ __launch_bounds__(256) void k_conv_sweep_f32(ConvArgs a, int R, int nseg, int nunit) {
+  constexpr int PL = kCsPix * kCsfPS;           // floats of one plane of a ring row
+  constexpr int XR = CH * PL, XN = 3 * XR;      // ring of three rows
+  constexpr int NU = 34 * CH * 4;               // 16-byte units of an input row (34 pixels)
+  constexpr int NLD = (NU + 63) / 64;
+  constexpr int D = 2;                          // input rows in flight in registers
+  __shared__ __attribute__((aligned(16))) float lds[4][XN];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int unit = blockIdx.x * 4 + wave, n = blockIdx.y;
+  if (unit >= nunit) return;  // the whole wave; nothing below synchronises waves
+  const int H = a.H, W = a.W, Cx = a.Cx;
+  // MS = 1: the two m-tiles of a band segment go to neighbouring waves (units 2 k, 2 k + 1)
+  const int mt0 = MS == 2 ? 0 : unit & 1, bs = MS == 2 ? unit : unit >> 1;
+  const int x0 = (bs / nseg) * kCsCols, y0 = (bs % nseg) * R;
+  float* X = lds[wave];
+  for (int e = lane * 4; e < XN; e += 256) *reinterpret_cast<f32x4*>(X + e) = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // weights (16-channel chunk packing): fragment (m, tap, chunk c), lane l = output channel
+  // 16 m + l % 16, input channels 16 c + 4 (l / 16) + [0, 4)
+  const float* wp = static_cast<const float*>(a.wp);
+  f32x4 w[MS][9][CH];
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        w[m][t][c] = *reinterpret_cast<const f32x4*>(wp + ((size_t)(((mt0 + m) * 9 + t) * CH + c) * 64 + lane) * 4);
+  f32x4 bias[MS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m) bias[m] = *reinterpret_cast<const f32x4*>(a.bias + 16 * (mt0 + m) + 4 * (lane >> 4));
+  int bo[2][3];  // B read offsets within a plane: pixel 16 s + l % 16 + dx, channels 4 (l / 16)
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) bo[s][dx] = (16 * s + (lane & 15) + dx) * kCsfPS + 4 * (lane >> 4);
+
+  // input rows: unit u = lane + 64 k is pixel u / (4 CH) (column x0 - 1 + u / (4 CH)), chunk
+  // (u % (4 CH)) / 4, channels 4 (u % 4) .. + 3 of it
+  const uint32_t img_bytes = (uint32_t)((size_t)H * W * Cx * sizeof(float));
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(static_cast<const float*>(a.x) + (size_t)n * H * W * Cx), 0, img_bytes, 0x00020000);
+  auto load_row = [&](int iy, f32x4 (&v)[NLD]) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int u = lane + 64 * k, px = u / (4 * CH), xc = x0 - 1 + px;
+      const bool in = u < NU && iy >= 0 && iy < H && xc >= 0 && xc < W;
+      const uint32_t off = in ? (uint32_t)((((size_t)iy * W + xc) * Cx + 4 * (u % (4 * CH))) * sizeof(float)) : img_bytes;
+      v[k] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+    }
+  };
+  auto store_row = [&](float* dst, const f32x4 (&v)[NLD]) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int u = lane + 64 * k, px = u / (4 * CH), wv = u % (4 * CH);
+      if (u < NU) *reinterpret_cast<f32x4*>(dst + (wv >> 2) * PL + px * kCsfPS + 4 * (wv & 3)) = v[k];
+    }
+  };
+  float* y = static_cast<float*>(a.y);
+  float* yp = static_cast<float*>(a.pool);
+  const int ylast = min(y0 + R, H) - 1;
+  f32x4 hprev[2][MS];  // the previous (even) row's outputs, for the pooled copy
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int m = 0; m < MS; ++m) hprev[s][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto emit = [&](const f32x4 (&acc)[2][MS], int o) {
+    const bool second = (o - y0) & 1;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int col = x0 + 16 * s + (lane & 15);
+#pragma unroll
+      for (int m = 0; m < MS; ++m) {
+        const int co = 16 * (mt0 + m) + 4 * (lane >> 4);
+        f32x4 v = acc[s][m];
+        if (a.relu) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q], 0.f);
+        }
+        if (col < W) *reinterpret_cast<f32x4*>(y + (((size_t)n * H + o) * W + col) * a.ldy + co) = v;
+        if (yp) {
+          if (second) {
+            f32x4 nb0, nb1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              nb0[q] = lane_xor1(hprev[s][m][q]);
+              nb1[q] = lane_xor1(v[q]);
+            }
+            if ((lane & 1) == 0 && col < W)
+              *reinterpret_cast<f32x4*>(yp + (((size_t)n * (H / 2) + o / 2) * (W / 2) + col / 2) * a.Cout + co) =
+                  ((hprev[s][m] + nb0) + (v + nb1)) * 0.25f;
+          } else {
+            hprev[s][m] = v;
+          }
+        }
+      }
+    }
+  };
+
+  // ring row k (input row y0 - 1 + k) sits in slot k % 3; rows 0..2 are staged up front and rows
+  // 3, 4 wait in registers gx[k % 2]
+  {
+    f32x4 v[NLD];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      load_row(y0 - 1 + k, v);
+      store_row(X + k * XR, v);
+    }
+  }
+  f32x4 gx[D][NLD];
+#pragma unroll
+  for (int k = 3; k < 3 + D; ++k) load_row(y0 - 1 + k, gx[k % D]);
+
+  int s0 = 0;  // slot of ring row i
+  auto step = [&](auto ph, int i) {
+    constexpr int G = (decltype(ph)::value + 3) % D;  // == (i + 3) % D
+    const int s1 = s0 == 2 ? 0 : s0 + 1, s2 = s1 == 2 ? 0 : s1 + 1;
+    const float* rows[3] = {X + s0 * XR, X + s1 * XR, X + s2 * XR};
+    wave_lds_sync();
+    f32x4 acc[2][MS];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int m = 0; m < MS; ++m) acc[s][m] = bias[m];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        __builtin_amdgcn_sched_barrier(0);  // one tap column's operands live at a time
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const f32x4 b = *reinterpret_cast<const f32x4*>(rows[dy] + c * PL + bo[s][dx]);
+#pragma unroll
+            for (int m = 0; m < MS; ++m) acc[s][m] = mma4(w[m][3 * dy + dx][c], b, acc[s][m]);
+          }
+      }
+    wave_lds_sync();
+    const int o = y0 + i;
+    if (o <= ylast) emit(acc, o);
+    store_row(X + s0 * XR, gx[G]);  // ring row i + 3 into the slot of row i
+    load_row(y0 + 2 + i + D, gx[G]);
+    s0 = s1;
+  };
+  for (int i = 0; i < R; i += 4) {  // R % 4 == 0 (host)
+    step(std::integral_constant<int, 0>{}, i);
+    step(std::integral_constant<int, 1>{}, i + 1);
+    step(std::integral_constant<int, 2>{}, i + 2);
+    step(std::integral_constant<int, 3>{}, i + 3);
+  }
+}
+
+// false: not this kernel's configuration (fp32 3x3 direct, 32 outputs, 16 or 32 inputs, no head)
+bool launch_conv_sweep_f32(const ConvArgs& a, hipStream_t st) {
+  if (a.mode != APS_CONV_DIRECT || a.C2 != 0 || a.Cout != 32 || a.ldy != 32 || a.hw || a.hside ||
+      (a.Cx != 16 && a.Cx != 32) || !a.bias)
+    return false;
+  if (a.pool && (a.H % 2 || a.W % 2)) return false;
+  if ((size_t)a.H * a.W * a.Cx * 4 >= (1ull << 31) || a.N > 65535) return false;
+  const long nband = (a.W + kCsCols - 1) / kCsCols;
+  // with 32 input channels each wave takes one of the two m-tiles (the weights of both would
+  // leave one wave per SIMD); the launch aims at about 2048 waves, two per SIMD
+  const int ms = a.Cx == 32 ? 1 : 2;
+  long R = std::max<long>(8, ((long)a.N * a.H * nband * (2 / ms) + 2047) / 2048);
+  R = (std::min<long>(R, a.H) + 3) / 4 * 4;  // four steps per loop iteration
+  const int nseg = (int)((a.H + R - 1) / R);
+  const long nunit = nband * nseg * (2 / ms);
+  if (nunit > (1L << 30) / 4) return false;
+  dim3 g((unsigned)((nunit + 3) / 4), a.N);
+  if (a.Cx == 32) k_conv_sweep_f32<2, 1><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  else k_conv_sweep_f32<1, 2><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
   return true;
 }
 

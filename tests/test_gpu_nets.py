@@ -93,52 +93,56 @@ def test_fused_head_bit_identical(ops, dtype, cout, K, cin):
     assert torch.equal(ymain, y)
 
 
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
 @pytest.mark.parametrize("relu", [True, False])
 @pytest.mark.parametrize("cin", [16, 32])
 @pytest.mark.parametrize("N,H,W", [(1, 1, 5), (2, 23, 37), (1, 67, 131), (3, 40, 72), (1, 130, 66)])
-def test_row_sweep_conv(ops, cin, relu, N, H, W):
-    """The bf16 3x3 layers with 16 or 32 inputs and 32 outputs (the row-sweep kernel): against
-    the FP64 oracle convolution of the same bf16 inputs (2e-2 of the layer magnitude, as every
-    bf16 layer), and bit for bit against the tiled kernel, whose main output the fused-head
-    entry point writes (same taps, same order).  The shapes cut bands of 32 columns and
-    segments of rows raggedly, include a one-row image, and for even sizes also the pooled copy."""
+def test_row_sweep_conv(ops, cin, relu, N, H, W, dtype):
+    """The 3x3 layers with 16 or 32 inputs and 32 outputs (the row-sweep kernels): against the
+    FP64 oracle convolution of the same inputs (2e-2 of the layer magnitude in bf16, 1e-5 in
+    fp32, as every layer), and bit for bit against the tiled kernel, whose main output the
+    fused-head entry point writes (same taps, same order).  The shapes cut bands of 32 columns
+    and segments of rows raggedly, include a one-row image, and for even sizes also the pooled
+    copy."""
     from paper_2602_08642_amd import _lib as L
     g = torch.Generator().manual_seed(N * 1000 + H * W + cin + relu)
     cout, K = 32, 34
-    x = torch.randn(N, H, W, cin, generator=g).to(DEV).to(torch.bfloat16)
+    x = torch.randn(N, H, W, cin, generator=g).to(DEV).to(dtype)
     sa = dict(name="a", cin=cin, cout=cout, k=3, relu=relu)
     sh = dict(name="h", cin=cout, cout=K, k=1, relu=False)
     wa = torch.randn(cout, 3, 3, cin, generator=g) / math.sqrt(9 * cin)
     ba = torch.randn(cout, generator=g) * 0.1
     wh = (torch.randn(K, 1, 1, cout, generator=g) / math.sqrt(cout)).numpy()
     net = ops.Net([sa, sh], {"a": (wa.numpy(), ba.numpy()),
-                             "h": (wh, np.zeros(K, np.float32))}, torch.bfloat16, DEV)
+                             "h": (wh, np.zeros(K, np.float32))}, dtype, DEV)
     _, pa, bb = net.layer("a")
     _, ph, bh = net.layer("h")
     y = ops.conv2d(x, sa, pa, bb)
-    wq = wa.to(torch.bfloat16).double()
+    wq = wa.to(dtype).double()
     ref = odens.conv2d_nhwc(x.double().cpu(), wq, ba.double())
     mag = odens.conv2d_nhwc(x.double().cpu().abs(), wq.abs(), ba.double().abs())
     if relu:
         ref = torch.relu(ref)
-    assert_mag_close(y.double().cpu(), ref, mag, 2e-2, what=f"row sweep {cin} {N}x{H}x{W}")
-    ks = ops.round_kstride(K, torch.bfloat16)
+    tol = 2e-2 if dtype == torch.bfloat16 else 1e-5
+    assert_mag_close(y.double().cpu(), ref, mag, tol, what=f"row sweep {dtype} {cin} {N}x{H}x{W}")
+    ks = ops.round_kstride(K, dtype)
+    dt = L.APS_BF16 if dtype == torch.bfloat16 else L.APS_F32
     ymain = torch.empty_like(y)
-    logits = torch.empty((N, H, W, ks), dtype=torch.bfloat16, device=DEV)
+    logits = torch.empty((N, H, W, ks), dtype=dtype, device=DEV)
     L.check(L.load().aps_conv2d_fwd_head(ops._p(x), None, N, H, W, cin, 0, L.APS_CONV_DIRECT, ops._p(pa),
-                                         ops._p(bb), cout, int(relu), ops._p(ph), ops._p(bh), K, L.APS_BF16,
+                                         ops._p(bb), cout, int(relu), ops._p(ph), ops._p(bh), K, dt,
                                          ops._p(ymain), cout, ops._p(logits), ks, ops._stream()), "head")
     assert torch.equal(ymain, y)
     if H % 2 == 0 and W % 2 == 0:
         y2 = torch.empty_like(y)
-        pooled = torch.full((N, H // 2, W // 2, cout), 3.0, dtype=torch.bfloat16, device=DEV)
+        pooled = torch.full((N, H // 2, W // 2, cout), 3.0, dtype=dtype, device=DEV)
         L.check(L.load().aps_conv2d_fwd_pool(ops._p(x), None, N, H, W, cin, 0, L.APS_CONV_DIRECT,
-                                             ops._p(pa), ops._p(bb), cout, int(relu), L.APS_BF16,
+                                             ops._p(pa), ops._p(bb), cout, int(relu), dt,
                                              ops._p(y2), ops._p(pooled), ops._stream()), "fwd_pool")
         assert torch.equal(y2, y)
         q = y.float().cpu()
         exp = ((q[:, 0::2, 0::2] + q[:, 0::2, 1::2]) + (q[:, 1::2, 0::2] + q[:, 1::2, 1::2])) * 0.25
-        assert torch.equal(pooled.cpu(), exp.to(torch.bfloat16))
+        assert torch.equal(pooled.cpu(), exp.to(dtype))
 
 
 @pytest.mark.parametrize("cin", [8, 16])
