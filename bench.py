@@ -264,7 +264,8 @@ def bench_config(name, steps, warmup, dev, seed=2602):
                  "what": "s = B everywhere, all-zero logits (box-weighted pyramid)"},
         roofline={"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                   "frac": round(achieved / peak, 4), "traffic": measured_traffic(name),
-                  "kernel": "k_conv (implicit-GEMM MFMA conv), all U-Net launches of one frame",
+                  "kernel": ("U-Net MFMA convolutions (row-sweep and tiled implicit-GEMM 3x3, 1x1 heads), "
+                             "all launches of one frame"),
                   "algorithmic_flop_per_frame": flops},
         filter_roofline={"bound": "hbm", "achieved": round(fgbs, 1), "peak": PEAK["hbm_GBps"],
                          "unit": "GB/s", "frac": round(fgbs / PEAK["hbm_GBps"], 4),
