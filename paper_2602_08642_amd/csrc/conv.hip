@@ -935,8 +935,8 @@ void launch_conv_lds_m(const ConvArgs& a, hipStream_t st) {
 }
 
 // ---- bf16 3x3 convolution with 32 output channels as a per-wave row sweep ----------------
-// For the full-resolution 32-channel layers (16 or 32 input channels), which move far more bytes
-// than they compute: the tiled blocks stage a tile and its weights, compute for a fraction of the
+// For the full-resolution 32-channel layers (16 or 32 input channels), and the half-resolution
+// 32 -> 64 layer as two such halves, which move far more bytes than they compute: the tiled blocks stage a tile and its weights, compute for a fraction of the
 // time and store, with too little work per block to hide the staging behind the other blocks of
 // a CU.  Here each wave runs on its own, with no block barrier: it owns a band of 32 output
 // columns and R output rows, keeps its weights in registers, and walks down the band one output
@@ -988,23 +988,26 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
   const int unit = blockIdx.x * 4 + wave, n = blockIdx.y;
   if (unit >= nunit) return;  // the whole wave; nothing below synchronises waves
   const int H = a.H, W = a.W;
-  const int x0 = (unit / nseg) * kCsCols, y0 = (unit % nseg) * R;
+  // 64 outputs: the two halves of a band segment go to neighbouring waves (units 2 k, 2 k + 1)
+  const int mt0 = a.Cout == 64 ? 2 * (unit & 1) : 0, bs = a.Cout == 64 ? unit >> 1 : unit;
+  const int x0 = (bs / nseg) * kCsCols, y0 = (bs % nseg) * R;
   T* X = lds[wave];
   T* O = X + XN;  // two output rows, [2][32 px][32 channels], chunks swizzled as cs_off<4>
   T* Ls = O + ON;
   for (int e = lane * 8; e < XN + ON; e += 512) zero8(X + e);
 
-  // weights of the chunk layout: fragment (m, tap), lane l = output channel 16 m + l % 16,
-  // input channels 8 (l / 16) .. + 7
+  // weights of the chunk layout: fragment (m-tile mt0 + m, tap), lane l = output channel
+  // 16 (mt0 + m) + l % 16, input channels 8 (l / 16) .. + 7
   const T* wp = static_cast<const T*>(a.wp);
   Frag<T> w[2][9];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int t = 0; t < 9; ++t) frag_load(w[m][t], wp + ((size_t)(m * 9 + t) * 64 + lane) * 8);
+    for (int t = 0; t < 9; ++t) frag_load(w[m][t], wp + ((size_t)((mt0 + m) * 9 + t) * 64 + lane) * 8);
   f32x4 bias[2];
 #pragma unroll
-  for (int m = 0; m < 2; ++m) bias[m] = *reinterpret_cast<const f32x4*>(a.bias + 16 * m + 4 * (lane >> 4));
+  for (int m = 0; m < 2; ++m)
+    bias[m] = *reinterpret_cast<const f32x4*>(a.bias + 16 * (mt0 + m) + 4 * (lane >> 4));
   // fused 1x1 head (HM m-tiles of logits): the packed head weights of the one 32-channel chunk
   // and the head biases, as the tiled kernel's epilogue holds them
   // (biases in LDS, read per row, to keep the weights and the row prefetch in registers)
@@ -1069,7 +1072,7 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
       for (int k = 0; k < 2; ++k) {
         const int q = lane + 64 * k, px = q >> 2, g = q & 3;
         if (x0 + px < W)
-          *reinterpret_cast<u16x8*>(y + (rowbase + x0 + px) * a.ldy + 8 * g) =
+          *reinterpret_cast<u16x8*>(y + (rowbase + x0 + px) * a.ldy + 16 * mt0 + 8 * g) =
               *reinterpret_cast<const u16x8*>(Ob + cs_off<4>(px, g));
       }
     }
@@ -1121,7 +1124,7 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
         for (int e = 0; e < 8; ++e)
           r[e] = ((bf2f(a0[e]) + bf2f(a1[e])) + (bf2f(b0[e]) + bf2f(b1[e]))) * 0.25f;
         const u16x4 lo = f2bf4(r[0], r[1], r[2], r[3]), hi = f2bf4(r[4], r[5], r[6], r[7]);
-        *reinterpret_cast<u16x8*>(yp + (((size_t)n * (H / 2) + o / 2) * (W / 2) + (x0 / 2 + xp)) * a.Cout + 8 * g) =
+        *reinterpret_cast<u16x8*>(yp + (((size_t)n * (H / 2) + o / 2) * (W / 2) + (x0 / 2 + xp)) * a.Cout + 16 * mt0 + 8 * g) =
             u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
       }
     }
@@ -1181,33 +1184,38 @@ __global__ __launch_bounds__(256) void k_conv_sweep(ConvArgs a, int R, int nseg,
   }
 }
 
-// false: not this kernel's configuration: bf16 3x3 direct, 32 outputs, 16 or 32 inputs; with
-// HM, the fused head (32 inputs, logits staged: kstride <= 16 HM, 16-byte rows and base), no pool
+// false: not this kernel's configuration: bf16 3x3 direct; 32 outputs from 16 or 32 inputs, or
+// 64 outputs from 32 (each wave one half, its neighbour the other); with HM, the fused head (32
+// inputs and outputs, logits staged: kstride <= 16 HM, 16-byte rows and base), no pool
 template <int HM>
 bool launch_conv_sweep(const ConvArgs& a, hipStream_t st) {
-  if (a.mode != APS_CONV_DIRECT || a.C2 != 0 || a.Cout != 32 || a.nchunk != 1 || !a.bias ||
-      (a.Cx != 16 && a.Cx != 32))
+  if (a.mode != APS_CONV_DIRECT || a.C2 != 0 || a.nchunk != 1 || !a.bias ||
+      !((a.Cout == 32 && (a.Cx == 16 || a.Cx == 32)) || (a.Cout == 64 && a.Cx == 32)))
     return false;
   if constexpr (HM == 0) {
-    if (a.hw || a.hside || a.ldy != 32) return false;
+    if (a.hw || a.hside || a.ldy != a.Cout) return false;
     if (a.pool && (a.H % 2 || a.W % 2)) return false;
   } else {
-    if (a.Cx != 32 || a.pool || !a.hw || !a.hb || !a.hy || a.hK > 16 * HM || a.hldy > 16 * HM ||
-        (a.hldy * 2) % 16 || (reinterpret_cast<uintptr_t>(a.hy) & 15) ||
+    if (a.Cx != 32 || a.Cout != 32 || a.pool || !a.hw || !a.hb || !a.hy || a.hK > 16 * HM ||
+        a.hldy > 16 * HM || (a.hldy * 2) % 16 || (reinterpret_cast<uintptr_t>(a.hy) & 15) ||
         (a.hside && (reinterpret_cast<uintptr_t>(a.hside) & 7)) || (a.store_main && a.ldy != 32))
       return false;
   }
   if ((size_t)a.H * a.W * a.Cx * 2 >= (1ull << 31) || a.N > 65535) return false;
-  const long nband = (a.W + kCsCols - 1) / kCsCols;
+  const long nband = (a.W + kCsCols - 1) / kCsCols, halves = a.Cout / 32;
   // rows per wave: a multiple of the prefetch depth (even, so pooled rows pair up in a segment)
-  long R = std::max<long>(8, ((long)a.N * a.H * nband + kCsWaves - 1) / kCsWaves);
+  long R = std::max<long>(8, ((long)a.N * a.H * nband * halves + kCsWaves - 1) / kCsWaves);
   R = (std::min<long>(R, a.H) + kCsDepth - 1) / kCsDepth * kCsDepth;
   const int nseg = (int)((a.H + R - 1) / R);
-  const long nunit = nband * nseg;
+  const long nunit = nband * nseg * halves;
   if (nunit > (1L << 30) / 4) return false;
   dim3 g((unsigned)((nunit + 3) / 4), a.N);
-  if (a.Cx == 32) k_conv_sweep<4, HM><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
-  else if constexpr (HM == 0) k_conv_sweep<2, 0><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  if constexpr (HM == 0) {
+    if (a.Cx == 32) k_conv_sweep<4, 0><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+    else k_conv_sweep<2, 0><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  } else {
+    k_conv_sweep<4, HM><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
+  }
   return true;
 }
 

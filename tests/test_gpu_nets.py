@@ -95,18 +95,18 @@ def test_fused_head_bit_identical(ops, dtype, cout, K, cin):
 
 @pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
 @pytest.mark.parametrize("relu", [True, False])
-@pytest.mark.parametrize("cin", [16, 32])
+@pytest.mark.parametrize("cin,cout", [(16, 32), (32, 32), (32, 64), (64, 64)])
 @pytest.mark.parametrize("N,H,W", [(1, 1, 5), (2, 23, 37), (1, 67, 131), (3, 40, 72), (1, 130, 66)])
-def test_row_sweep_conv(ops, cin, relu, N, H, W, dtype):
-    """The 3x3 layers with 16 or 32 inputs and 32 outputs (the row-sweep kernels): against the
-    FP64 oracle convolution of the same inputs (2e-2 of the layer magnitude in bf16, 1e-5 in
-    fp32, as every layer), and bit for bit against the tiled kernel, whose main output the
-    fused-head entry point writes (same taps, same order).  The shapes cut bands of 32 columns
-    and segments of rows raggedly, include a one-row image, and for even sizes also the pooled
-    copy."""
+def test_row_sweep_conv(ops, cin, cout, relu, N, H, W, dtype):
+    """The 3x3 layers with 16 or 32 inputs and 32 or 64 outputs (the row-sweep kernels; 64 -> 64
+    runs the tiled kernel on both sides, a control): against the FP64 oracle convolution of the
+    same inputs (2e-2 of the layer magnitude in bf16, 1e-5 in fp32, as every layer), and bit for
+    bit against the tiled kernel, whose main output the fused-head entry point writes (same taps,
+    same order).  The shapes cut bands of 32 columns and segments of rows raggedly, include a
+    one-row image, and for even sizes also the pooled copy."""
     from paper_2602_08642_amd import _lib as L
-    g = torch.Generator().manual_seed(N * 1000 + H * W + cin + relu)
-    cout, K = 32, 34
+    g = torch.Generator().manual_seed(N * 1000 + H * W + cin + cout + relu)
+    K = 34
     x = torch.randn(N, H, W, cin, generator=g).to(DEV).to(dtype)
     sa = dict(name="a", cin=cin, cout=cout, k=3, relu=relu)
     sh = dict(name="h", cin=cout, cout=K, k=1, relu=False)
