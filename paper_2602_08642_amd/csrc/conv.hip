@@ -1221,17 +1221,19 @@ bool launch_conv_sweep(const ConvArgs& a, hipStream_t st) {
 
 // ---- fp32 form of the row sweep ------------------------------------------------------------
 // The same per-wave sweep for the fp32 networks' 32-channel full-resolution layers (16 or 32
-// input channels, 32 outputs, no head): on the tiled fp32 kernel these run at 57-68 % of the
-// MFMA peak against 81-87 % for the wider layers, each block computing two 16-channel chunks at
-// most for one staged tile.  Here the weights (2 m-tiles x 9 taps x CH chunks of 16 channels) stay
-// in registers and each input row is read from HBM once per band into a ring of three LDS rows,
-// each held as CH planes of [36 px][20 floats] (the tiled kernel's 80-byte pixel pitch, so the
-// 16 lanes of a B read hit distinct banks).  Output row o is summed in the tiled kernel's order:
-// 16-channel chunks outer, then taps dx, dy, four K = 4 MFMAs per tap, from the bias; so the two
-// kernels give the same bits.  Epilogue as lds_epilogue_f32: ReLU, 16-byte stores per lane, and
-// with a pooled output the 2x2 mean of the previous and the current row (neighbour column by DPP)
-// in the POOL2 order.  Ring row i + 3 is staged into the slot of row i after this step's reads of
-// it (one wave's LDS operations complete in program order).
+// input channels, 32 outputs, no head) and the half-resolution 32 -> 64 layer.  On the tiled fp32
+// kernel these run at 57-70 % of the MFMA peak against 81-87 % for the wider layers, each block
+// computing two 16-channel chunks at most for one staged tile.  Here the weights (9 taps x CH
+// chunks of 16 channels for MS m-tiles: both with 16 input channels; with 32 one per wave, its
+// neighbour waves taking the others, so that two waves fit a SIMD) stay in registers and each
+// input row is read from HBM once per band into a ring of three LDS rows, each held as CH planes
+// of [36 px][20 floats] (the tiled kernel's 80-byte pixel pitch, so the 16 lanes of a B read hit
+// distinct banks).  Output row o is summed in the tiled kernel's order: 16-channel chunks outer,
+// then taps dx, dy, four K = 4 MFMAs per tap, from the bias; so the two kernels give the same
+// bits.  Epilogue as lds_epilogue_f32: ReLU, 16-byte stores per lane, and with a pooled output
+// the 2x2 mean of the previous and the current row (neighbour column by DPP) in the POOL2 order.
+// Ring row i + 3 is staged into the slot of row i after this step's reads of it (one wave's LDS
+// operations complete in program order).
 constexpr int kCsfPS = 20;       // floats per staged pixel of a 16-channel plane
 
 template <int CH, int MS>
@@ -1246,8 +1248,9 @@ __global__ __launch_bounds__(256) void k_conv_sweep_f32(ConvArgs a, int R, int n
   const int unit = blockIdx.x * 4 + wave, n = blockIdx.y;
   if (unit >= nunit) return;  // the whole wave; nothing below synchronises waves
   const int H = a.H, W = a.W, Cx = a.Cx;
-  // MS = 1: the two m-tiles of a band segment go to neighbouring waves (units 2 k, 2 k + 1)
-  const int mt0 = MS == 2 ? 0 : unit & 1, bs = MS == 2 ? unit : unit >> 1;
+  // MS = 1: the Cout / 16 m-tiles of a band segment go to neighbouring waves
+  const int nm = a.Cout >> 4;
+  const int mt0 = MS == 2 ? 0 : unit % nm, bs = MS == 2 ? unit : unit / nm;
   const int x0 = (bs / nseg) * kCsCols, y0 = (bs % nseg) * R;
   float* X = lds[wave];
   for (int e = lane * 4; e < XN; e += 256) *reinterpret_cast<f32x4*>(X + e) = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -1388,21 +1391,22 @@ __global__ __launch_bounds__(256) void k_conv_sweep_f32(ConvArgs a, int R, int n
   }
 }
 
-// false: not this kernel's configuration (fp32 3x3 direct, 32 outputs, 16 or 32 inputs, no head)
+// false: not this kernel's configuration (fp32 3x3 direct, no head: 32 outputs from 16 or 32
+// inputs, 64 from 32)
 bool launch_conv_sweep_f32(const ConvArgs& a, hipStream_t st) {
-  if (a.mode != APS_CONV_DIRECT || a.C2 != 0 || a.Cout != 32 || a.ldy != 32 || a.hw || a.hside ||
-      (a.Cx != 16 && a.Cx != 32) || !a.bias)
+  if (a.mode != APS_CONV_DIRECT || a.C2 != 0 || a.ldy != a.Cout || a.hw || a.hside || !a.bias ||
+      !((a.Cout == 32 && (a.Cx == 16 || a.Cx == 32)) || (a.Cout == 64 && a.Cx == 32)))
     return false;
   if (a.pool && (a.H % 2 || a.W % 2)) return false;
   if ((size_t)a.H * a.W * a.Cx * 4 >= (1ull << 31) || a.N > 65535) return false;
   const long nband = (a.W + kCsCols - 1) / kCsCols;
-  // with 32 input channels each wave takes one of the two m-tiles (the weights of both would
-  // leave one wave per SIMD); the launch aims at about 2048 waves, two per SIMD
-  const int ms = a.Cx == 32 ? 1 : 2;
-  long R = std::max<long>(8, ((long)a.N * a.H * nband * (2 / ms) + 2047) / 2048);
+  // with 32 input channels each wave takes one m-tile (the weights of two would leave one wave
+  // per SIMD), its neighbours the others; the launch aims at about 2048 waves, two per SIMD
+  const int wps = a.Cx == 32 ? a.Cout / 16 : 1;  // waves per band segment
+  long R = std::max<long>(8, ((long)a.N * a.H * nband * wps + 2047) / 2048);
   R = (std::min<long>(R, a.H) + 3) / 4 * 4;  // four steps per loop iteration
   const int nseg = (int)((a.H + R - 1) / R);
-  const long nunit = nband * nseg * (2 / ms);
+  const long nunit = nband * nseg * wps;
   if (nunit > (1L << 30) / 4) return false;
   dim3 g((unsigned)((nunit + 3) / 4), a.N);
   if (a.Cx == 32) k_conv_sweep_f32<2, 1><<<g, 256, 0, st>>>(a, (int)R, nseg, (int)nunit);
