@@ -96,10 +96,11 @@ int aps_conv_pack_weights(const float* w, int Cout, int ksize, int Cin, int dtyp
  *   APS_CONV_UP2_CAT: x [N,H/2,W/2,Cx] nearest-2x upsampled, concatenated with x2 [N,H,W,C2]
  *                     (channels [0,Cx) from x, [Cx,Cx+C2) from x2)
  * Cx and C2 must be multiples of 8.  dtype/y_dtype: (F32,F32), (BF16,BF16) or (BF16,F32).
- * For 3x3 layers with Cx + C2 > 16 and (F32,F32) or (BF16,BF16), the fp32 sum of each output
- * has one order whichever kernel the shape selects (the bias, then 16-channel (fp32) or
- * 32-channel (bf16) input chunks, taps dx outer and dy inner), so this call, the main output of
- * aps_conv2d_fwd_head(_ex) and y of aps_conv2d_fwd_pool agree bit for bit. */
+ * For 3x3 layers with Cx + C2 > 16, Cout a multiple of 16 above 16, ldy a multiple of 4 and
+ * (F32,F32) or (BF16,BF16), the fp32 sum of each output has one order whichever kernel the
+ * shape selects (the bias, then 16-channel (fp32) or 32-channel (bf16) input chunks, taps dx
+ * outer and dy inner), so this call, the main output of aps_conv2d_fwd_head(_ex) and y of
+ * aps_conv2d_fwd_pool agree bit for bit. */
 int aps_conv2d_fwd(const void* x, const void* x2, int N, int H, int W, int Cx, int C2, int mode,
                    const void* packed_w, const float* bias, int Cout, int ksize, int relu,
                    int dtype, void* y, int ldy, int y_dtype, void* stream);
